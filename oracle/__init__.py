@@ -1,0 +1,267 @@
+"""FP64 CPU oracle (ctypes front-end of ``goac_oracle.c``).
+
+TEST INFRASTRUCTURE: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` import this package. It shares no code with the HIP
+library and never calls it; the product path never calls this.
+
+Every routine is a plain transcription of the definition or of the algorithm's
+steps (see the C source for the per-function citations of the paper). Eq. 1's
+configuration count is implemented here in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "goac_oracle.c")
+_LIB = os.path.join(_HERE, "libgoac_oracle.so")
+
+# Counter tags of the Philox draws (fourth counter word, low byte)
+TAG_MC, TAG_INIT, TAG_SEL, TAG_X, TAG_MUT, TAG_REMC = 1, 2, 3, 4, 5, 6
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class ChainStats(C.Structure):
+    _fields_ = [("t", C.c_uint64), ("accepts", C.c_uint64), ("updates", C.c_uint64),
+                ("hash", C.c_uint64), ("E", C.c_double), ("best_E", C.c_double),
+                ("min_margin", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_philox.argtypes = [P, P, P]
+        L.or_trial_hash.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.or_trial_hash.restype = C.c_uint64
+        L.or_coulomb_constant.restype = C.c_double
+        L.or_ewald_defaults.argtypes = [P, P, P, P]
+        L.or_ewald_entry.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_int, P]
+        L.or_ewald_matrix.argtypes = [P, C.c_int64, P, C.c_double, C.c_double, C.c_int, P]
+        L.or_ewald_energy.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_double, C.c_int]
+        L.or_ewald_energy.restype = C.c_double
+        L.or_energy_q.argtypes = [P, C.c_int64, P]
+        L.or_energy_q.restype = C.c_double
+        L.or_energies.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
+        L.or_init_occupations.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int64, C.c_uint64,
+                                          C.c_uint32, C.c_uint32, P]
+        L.or_mc_run.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int64, P, P, P, P,
+                                C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
+                                P, C.c_int32, C.c_uint64, P, C.c_int32]
+        L.or_remc_exchange.argtypes = [C.c_int32, P, P, P, C.c_uint64, C.c_uint64, C.c_uint32, P]
+        L.or_ga_generation.argtypes = [C.c_int64, P, C.c_int32, C.c_int64, P, P, C.c_uint64,
+                                       C.c_uint32, C.c_int32, C.c_double, P]
+        L.or_topk.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int32, P, P]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------- RNG
+
+def philox(ctr, key):
+    """Philox4x32-10 of one 4-word counter and 2-word key."""
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+def trial_hash(t, i, j, acc):
+    return int(lib().or_trial_hash(t, i, j, acc))
+
+
+# ---------------------------------------------------------------- Ewald
+
+def coulomb_constant():
+    return float(lib().or_coulomb_constant())
+
+
+def ewald_defaults(lattice, alpha=0.0, rcut=0.0, kmax=0):
+    lat = _c(lattice, np.float64).reshape(-1)
+    a = np.array([alpha], np.float64)
+    r = np.array([rcut], np.float64)
+    k = np.array([kmax], np.int32)
+    lib().or_ewald_defaults(_p(lat), _p(a), _p(r), _p(k))
+    return float(a[0]), float(r[0]), int(k[0])
+
+
+def ewald_matrix(lattice, pos, alpha=0.0, rcut=0.0, kmax=0):
+    """Full n x n FP64 pair matrix V (eV per e^2)."""
+    lat = _c(lattice, np.float64).reshape(-1)
+    pos = _c(pos, np.float64)
+    n = len(pos)
+    V = np.zeros((n, n), np.float64)
+    rc = lib().or_ewald_matrix(_p(lat), n, _p(pos), alpha, rcut, kmax, _p(V))
+    if rc:
+        raise ValueError("bad Ewald parameters")
+    return V
+
+
+def ewald_entry(lattice, pos, i, j, alpha=0.0, rcut=0.0, kmax=0):
+    lat = _c(lattice, np.float64).reshape(-1)
+    pos = _c(pos, np.float64)
+    out = np.zeros(1, np.float64)
+    if lib().or_ewald_entry(_p(lat), _p(pos), int(i), int(j), alpha, rcut, kmax, _p(out)):
+        raise ValueError("bad Ewald parameters")
+    return float(out[0])
+
+
+def ewald_energy(lattice, pos, q, alpha=0.0, rcut=0.0, kmax=0):
+    """Ewald energy in the structure-factor form (an independent route to 1/2 q^T V q)."""
+    lat = _c(lattice, np.float64).reshape(-1)
+    pos = _c(pos, np.float64)
+    q = _c(q, np.float64)
+    return float(lib().or_ewald_energy(_p(lat), len(pos), _p(pos), _p(q), alpha, rcut, kmax))
+
+
+def cell_matrix(cell):
+    e = cell["ewald"]
+    return ewald_matrix(cell["lattice"], cell["pos"], e["alpha"], e["rcut"], e["kmax"])
+
+
+# ---------------------------------------------------------------- energies
+
+def energy_q(V, q):
+    V = _c(V, np.float64)
+    q = _c(q, np.float64)
+    return float(lib().or_energy_q(_p(V), len(q), _p(q)))
+
+
+def energies(V, occ, charge):
+    V = _c(V, np.float64)
+    occ = _c(np.atleast_2d(occ), np.uint8)
+    charge = _c(charge, np.float64)
+    P, n = occ.shape
+    E = np.zeros(P, np.float64)
+    lib().or_energies(_p(V), n, P, _p(occ), _p(charge), _p(E))
+    return E
+
+
+# ---------------------------------------------------------------- stochastic routines
+
+def init_occupations(cell, C_, seed, chain_base=0, instance=0):
+    sub = _c(cell["sublattice"], np.int32)
+    spc = _c(cell["species"], np.uint8)
+    n = len(sub)
+    occ = np.zeros((C_, n), np.uint8)
+    rc = lib().or_init_occupations(n, _p(sub), _p(spc), len(cell["charge"]), C_, seed,
+                                   chain_base, instance, _p(occ))
+    if rc:
+        raise ValueError("bad problem")
+    return occ
+
+
+class MCState:
+    """State of C chains: occupations, perm arrays, best occupations and counters."""
+
+    def __init__(self, occ):
+        self.occ = _c(occ, np.uint8).copy()
+        self.perm = None
+        self.best_occ = self.occ.copy()
+        self.stats = (ChainStats * len(self.occ))()
+
+    def field(self, name):
+        return np.array([getattr(s, name) for s in self.stats])
+
+
+def mc_run(V, cell, state: MCState, seed, n_trials, kT, block_len, chain_base=0, instance=0,
+           kT_row=None):
+    """Advance every chain in ``state`` by n_trials trials (resumable)."""
+    V = _c(V, np.float64)
+    sub = _c(cell["sublattice"], np.int32)
+    charge = _c(cell["charge"], np.float64)
+    n = len(sub)
+    C_ = len(state.occ)
+    M = int((sub >= 0).sum())
+    init = state.perm is None
+    if init:
+        state.perm = np.zeros((C_, max(M, 1)), np.int32)
+    kT = _c(np.atleast_2d(kT), np.float64)
+    nb = kT.shape[1]
+    rows = None if kT_row is None else _c(kT_row, np.int32)
+    rc = lib().or_mc_run(_p(V), n, _p(sub), _p(charge), len(charge), C_, _p(state.occ),
+                         _p(state.perm), _p(state.best_occ), C.cast(state.stats, C.c_void_p),
+                         seed, chain_base, instance, n_trials, _p(kT), nb, block_len,
+                         None if rows is None else _p(rows), 1 if init else 0)
+    if rc:
+        raise ValueError("oracle MC failed")
+    return state
+
+
+def remc_exchange(kT_ladder, E, slot, x, seed, group=0):
+    kT = _c(kT_ladder, np.float64)
+    E = _c(E, np.float64)
+    slot = _c(slot, np.int32).copy()
+    acc = np.zeros(len(kT), np.uint8)
+    lib().or_remc_exchange(len(kT), _p(kT), _p(E), _p(slot), x, seed, group, _p(acc))
+    return slot, acc
+
+
+def ga_generation(cell, pop, E, seed, g, n_elite=8, p_mut=0.2):
+    sub = _c(cell["sublattice"], np.int32)
+    pop = _c(pop, np.uint8)
+    E = _c(E, np.float64)
+    P, n = pop.shape
+    out = np.zeros_like(pop)
+    rc = lib().or_ga_generation(n, _p(sub), len(cell["charge"]), P, _p(pop), _p(E), seed, g,
+                                n_elite, p_mut, _p(out))
+    if rc:
+        raise ValueError("oracle GA failed (%d)" % rc)
+    return out
+
+
+def topk(V, occ, charge, k):
+    V = _c(V, np.float64)
+    occ = _c(np.atleast_2d(occ), np.uint8)
+    charge = _c(charge, np.float64)
+    P, n = occ.shape
+    kk = min(k, P)
+    idx = np.zeros(kk, np.int64)
+    E = np.zeros(kk, np.float64)
+    lib().or_topk(_p(V), n, P, _p(occ), _p(charge), k, _p(idx), _p(E))
+    return idx, E
+
+
+def num_threads():
+    return int(lib().or_num_threads())
+
+
+# ---------------------------------------------------------------- Eq. 1
+
+def log10_configurations(counts_per_site):
+    """log10 C of Eq. 1, C = prod_s P_s! / prod_e N_{s,e}!, for per-site lists of
+    element counts (a vacancy counts as an element)."""
+    tot = 0.0
+    for counts in counts_per_site:
+        P = sum(counts)
+        tot += math.lgamma(P + 1) - sum(math.lgamma(c + 1) for c in counts)
+    return tot / math.log(10.0)

@@ -1,0 +1,131 @@
+"""Pins of the oracle's configuration energies (Methodology, "Cluster Expansion of
+Coulomb Energy" and Eq. 2; "Implementation and Theoretical Background", Eq. 1;
+Results, Eq. 3)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import supercells as S
+
+
+def test_eq1_counts_match_paper():
+    # Eq. 1 with vacancies counted as an element reproduces every count printed:
+    # NaCl 3x3x3 (1e64), FeSbO4 3x3x14 (1e75), LLZO 2x2x1 (1e159) and the Table 1
+    # O3 high-entropy cells (9 Na and 9 TM positions per sqrt(3) cell; Na 2/3 with
+    # vacancies; Li/Fe/Co/Ni 1/6 each, Mn 1/3).
+    assert round(O.log10_configurations([[108, 108]])) == 64
+    assert round(O.log10_configurations([[126, 126]])) == 75
+    assert round(O.log10_configurations([[192, 288], [95, 1], [29, 35]])) == 159
+    table = {(2, 2, 1): 31, (2, 2, 2): 64, (4, 4, 1): 132, (4, 4, 2): 269,
+             (6, 6, 1): 303, (8, 8, 1): 543, (6, 6, 2): 611, (6, 6, 3): 920}
+    for (a, b, c), expo in table.items():
+        m = a * b * c
+        val = O.log10_configurations([[6 * m, 3 * m], [3 * m // 2] * 4 + [3 * m]])
+        assert round(val) == expo
+
+
+def test_eq1_brute_force_tiny():
+    # brute-force count of distinct arrangements on a tiny two-site problem
+    arr = [0, 0, 1, 2]
+    n1 = len(set(itertools.permutations(arr)))
+    n2 = len(set(itertools.permutations([0, 1, 1])))
+    assert round(10 ** O.log10_configurations([[2, 1, 1], [1, 2]])) == n1 * n2
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    c = S.config1()
+    return c, O.cell_matrix(c)
+
+
+def _substructure_energy(cell, q):
+    e = cell["ewald"]
+    return O.ewald_energy(cell["lattice"], cell["pos"], q, e["alpha"], e["rcut"], e["kmax"])
+
+
+def test_cluster_expansion_from_substructures(cfg1):
+    """Eq. 2 built the paper's way: E_const from the fixed ions alone, alpha from
+    the fixed ions plus one placed ion minus E_const, beta from two placed ions
+    minus both single-ion structures plus E_const, every term an Ewald energy of a
+    charged sub-structure (structure-factor route, independent of the pair
+    matrix). Summed over the binary x of a configuration it must equal the double
+    loop 1/2 q^T V q (the expansion is exact for point charges)."""
+    cell, V = cfg1
+    sub = cell["sublattice"]
+    fixed = np.where(sub < 0, cell["charge"][cell["species"]], 0.0)
+    mob = np.nonzero(sub >= 0)[0]
+    spcs = [1, 2]
+    E0 = _substructure_energy(cell, fixed)
+    alpha = {}
+    for s in spcs:
+        for j in mob:
+            q = fixed.copy()
+            q[j] = cell["charge"][s]
+            alpha[s, j] = _substructure_energy(cell, q) - E0
+    rng = np.random.default_rng(11)
+    occs = S.random_occupations(cell, 3, seed=4)
+    # beta only for the pairs the three test configurations need
+    for occ in occs:
+        placed = [(occ[j], j) for j in mob]
+        e = E0 + sum(alpha[s, j] for s, j in placed)
+        for (s, j), (t, l) in itertools.combinations(placed, 2):
+            q = fixed.copy()
+            q[j] = cell["charge"][s]
+            q[l] = cell["charge"][t]
+            e2 = _substructure_energy(cell, q)
+            q1 = fixed.copy(); q1[j] = cell["charge"][s]
+            q2 = fixed.copy(); q2[l] = cell["charge"][t]
+            beta = e2 - _substructure_energy(cell, q1) - _substructure_energy(cell, q2) + E0
+            e += beta
+        ref = O.energies(V, occ, cell["charge"])[0]
+        assert abs(e - ref) < 1e-9 * abs(ref)
+    assert rng is not None
+
+
+def test_exhaustive_table_translation_invariance(cfg1):
+    """All 12870 energies of config 1; a lattice translation that maps the cation
+    positions onto themselves must leave every energy unchanged."""
+    cell, V = cfg1
+    occ = S.config1_exhaustive_occupations(cell)
+    E = O.energies(V, occ, cell["charge"])
+    pos = cell["pos"]
+    lat = cell["lattice"]
+    shift = np.array([2.1, 2.1, 0.0])            # an FCC translation of the cation lattice
+    inv = np.linalg.inv(lat)
+    moved = (pos + shift) @ inv
+    moved -= np.floor(moved + 1e-9)
+    frac = pos @ inv
+    frac -= np.floor(frac + 1e-9)
+    perm = np.array([np.argmin(np.linalg.norm(((frac - m + 0.5) % 1.0) - 0.5, axis=1)) for m in moved])
+    assert sorted(perm.tolist()) == list(range(len(pos)))
+    occ_t = np.empty_like(occ)
+    occ_t[:, perm] = occ
+    E_t = O.energies(V, occ_t, cell["charge"])
+    assert np.abs(E_t - E).max() < 1e-10
+    # a sample against the structure-factor route
+    for p in (0, 4321, 12869):
+        q = cell["charge"][occ[p]]
+        assert abs(_substructure_energy(cell, q) - E[p]) < 1e-10 * abs(E[p])
+
+
+def test_madelung_of_the_nacl_optimum():
+    # the alternating arrangement of the half-filled NaCl workload has the
+    # Madelung energy (Eq. 3 with r = 2.81 A and 216 ions)
+    cell = S.nacl_half(3, 5.62)
+    lat, pos, kind = S.rocksalt_conventional(3, 3, 3, 5.62)
+    q = np.where(kind == 0, 1.0, -1.0)
+    V = O.ewald_matrix(cell["lattice"], cell["pos"])
+    E = O.energy_q(V, q)
+    M = 2.81 * abs(E) / (108 * O.coulomb_constant())
+    assert abs(M - 1.747565) < 5e-7
+
+
+def test_energy_is_quadratic_form_of_matrix(cfg1):
+    # energies of a batch equal the single-row routine
+    cell, V = cfg1
+    occ = S.random_occupations(cell, 5, seed=1)
+    E = O.energies(V, occ, cell["charge"])
+    for p in range(5):
+        assert E[p] == O.energy_q(V, cell["charge"][occ[p]])
