@@ -1,0 +1,283 @@
+/*
+ * goac.h -- C ABI of the MI355X (gfx950) library for the pairwise Coulomb
+ * cluster-expansion optimiser of Koester, Binninger and Kaghazchi,
+ * "Optimization of Coulomb Energies in Gigantic Configurational Spaces of
+ * Multi-Element Ionic Crystals" (arXiv 2409.08808).
+ *
+ * Conventions shared by every entry point
+ *   - Units: positions in Angstrom, charges in e, energies in eV, kT in eV.
+ *   - Memory: arguments named *_host are host pointers, *_dev device pointers of
+ *     the context's device. The caller owns every buffer it passes and must keep
+ *     it alive until the context's stream has passed the call; the library
+ *     keeps no caller pointer once a call returns. The library owns the
+ *     context, problems, chain sets and their internal device memory.
+ *   - Asynchrony: device work is queued on the context's stream; outputs are
+ *     valid once that stream has synchronised. Argument, shape and composition
+ *     errors are found before anything is queued and returned synchronously.
+ *     A device fault surfaces as GOAC_EHIP on a later call.
+ *   - Errors: every call returns a goac_status; goac_last_error() describes the
+ *     last failure on a context. Nothing is thrown across the ABI.
+ *   - Threading: one context per host thread.
+ *   - Layouts: matrices are row-major. An occupation is one uint8 species id per
+ *     site; a population of P occupations of an n-site cell is P x n row-major.
+ */
+#ifndef GOAC_H
+#define GOAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GOAC_OK = 0,
+    GOAC_EINVAL = -1,      /* bad argument, shape or composition                 */
+    GOAC_ENOMEM = -2,      /* device allocation failed                           */
+    GOAC_EHIP = -3,        /* HIP runtime error or an earlier device fault       */
+    GOAC_ENOTNEUTRAL = -4, /* the cell's total charge is not zero                */
+    GOAC_EINEXACT = -5,    /* a shifted charge is not exact in bfloat16          */
+    GOAC_EDRIFT = -6,      /* the FP32 field left its error budget (see mc_sweep) */
+    GOAC_ESTATE = -7       /* object used with the wrong context or precision    */
+} goac_status;
+
+/* Arithmetic of energies and of the Monte Carlo field.
+ *   GOAC_FP64  : FP64 field and FP64 pair matrix throughout.
+ *   GOAC_MIXED : FP32 field phi with periodic FP64 re-anchoring and an exact
+ *                FP64 decision fallback (Monte Carlo); bfloat16 hi+lo split of the
+ *                pair matrix with FP32 accumulation on the matrix cores
+ *                (energies). */
+typedef enum { GOAC_FP64 = 0, GOAC_MIXED = 1 } goac_precision;
+
+typedef struct goac_ctx goac_ctx;
+typedef struct goac_problem goac_problem;
+typedef struct goac_chains goac_chains;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or
+ * NULL for the null stream). The stream is borrowed, not owned. */
+goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** out);
+void goac_ctx_destroy(goac_ctx* ctx);
+/* Message of the last failed call on ctx; valid until the next call on ctx. */
+const char* goac_last_error(const goac_ctx* ctx);
+/* Block until the context's stream is idle; reports pending device errors. */
+goac_status goac_ctx_synchronize(goac_ctx* ctx);
+
+/* ---------------------------------------------------------------- Ewald (a1) */
+
+/* Parameters of the Ewald split. A value <= 0 selects the default:
+ * alpha = 5 / volume^(1/3) (1/A), rcut = 6 / alpha (A), and kmax = ceil(12 alpha
+ * |a|_max / (2 pi)), the radius of the sphere of integer reciprocal indices
+ * n1^2 + n2^2 + n3^2 <= kmax^2, n != 0. */
+typedef struct {
+    double alpha;
+    double rcut;
+    int32_t kmax;
+    int32_t reserved;
+} goac_ewald_params;
+
+/* The periodic point-charge pair matrix (Methodology, "Cluster Expansion of
+ * Coulomb Energy": Ewald summation of point charges, for which the second-order
+ * expansion is exact):
+ *   V_ij = k_e [ sum_{m: 0<|r+mA|<rcut} erfc(alpha|r+mA|)/|r+mA|
+ *              + (4 pi/W) sum_{n != 0, |n| <= kmax} e^{-G^2/4alpha^2}/G^2 cos(G.r)
+ *              - pi/(W alpha^2) ] - delta_ij k_e 2 alpha/sqrt(pi),
+ * r = r_j - r_i, W the cell volume, G = n B, k_e = e/(4 pi eps0) (CODATA 2018),
+ * tin-foil boundary, neutralising background kept in every entry, so that
+ * E(q) = 1/2 q^T V q for any neutral q.
+ *   lattice_host : 9 doubles, rows are the lattice vectors (A)
+ *   pos_host     : n x 3 Cartesian positions (A)
+ *   V_dev        : n x n FP64 output, row-major, caller-owned
+ * Errors: EINVAL for n <= 0, a singular lattice or NULL pointers. */
+goac_status goac_build_ewald(goac_ctx* ctx, const double lattice_host[9], int64_t n,
+                             const double* pos_host, const goac_ewald_params* params,
+                             double* V_dev);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Set up an optimisation problem (Eq. 2): sites with sublattice < 0 are fixed,
+ * the others are mobile positions of site class `sublattice` whose species may
+ * be exchanged; the species counts per sublattice in `species_host` are the
+ * occupancy targets every occupation must keep.
+ *   V_dev         : n x n FP64 pair matrix (device); copied, not retained
+ *   sublattice_host: n int32 (-1 fixed, else 0..15)
+ *   species_host  : n uint8 species ids (< n_species <= 32): fixed-site species
+ *                   and the reference composition of the mobile positions
+ *   charge_host   : n_species FP64 valences
+ * The problem holds the mobile block V_mm in FP64, FP32 and a bfloat16 hi+lo
+ * split, its diagonal, the field of the fixed ions h = V_mf q_f, their energy
+ * E_ff, and for each sublattice the integer c nearest its mean charge with
+ * h~ = h + V_mm c and E~ = E_ff + c^T h + 1/2 c^T V_mm c (FP64).
+ * Errors: EINVAL (shapes, ids, more than 65535 mobile positions),
+ * ENOTNEUTRAL if |sum q| > 1e-9. */
+goac_status goac_problem_create(goac_ctx* ctx, const double* V_dev, int64_t n,
+                                const int32_t* sublattice_host, const uint8_t* species_host,
+                                int32_t n_species, const double* charge_host,
+                                goac_problem** out);
+void goac_problem_destroy(goac_problem* pb);
+
+typedef struct {
+    int64_t n;              /* sites                                          */
+    int64_t M;              /* mobile positions                               */
+    int32_t n_sublattices;
+    int32_t n_species;
+    double E_fixed;         /* E_ff                                            */
+    int32_t mixed_exact;    /* 1 if every shifted charge is bfloat16-exact     */
+    int32_t reserved;
+} goac_problem_info;
+goac_status goac_problem_get_info(const goac_problem* pb, goac_problem_info* out);
+
+/* Random valid starts (SI, "Random"): per chain c and sublattice s, the
+ * canonical species sequence shuffled by Fisher-Yates with
+ * m = (r (k+1)) >> 32, r the first word of Philox4x32-10 at counter
+ * (k, s, chain_base + c, instance << 8 | 2), key = seed.
+ *   occ_dev : C x n output (fixed sites copied from the problem). */
+goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64_t seed, uint32_t chain_base,
+                                  uint32_t instance, uint8_t* occ_dev);
+
+/* ---------------------------------------------------------------- energies (a2) */
+
+/* Configuration energies E_p = 1/2 q_p^T V q_p of P occupations, evaluated in the
+ * reduced form of Eq. 2, E_p = E_ff + q^T h + 1/2 q^T V_mm q over the mobile
+ * block (fixed-site entries of occ are ignored).
+ *   GOAC_FP64  : FP64 matrix-core product Q V_mm and FP64 row dot.
+ *   GOAC_MIXED : q = c + dq with the exact integer shift c; Phi = dQ V_hi + dQ
+ *                V_lo on bfloat16 matrix cores with FP32 accumulation, then
+ *                E_p = E~ + sum_k dq_k (h~_k + Phi_k / 2) in FP64.
+ *   occ_dev : P x n uint8;  E_dev : P FP64 output.
+ * Errors: EINVAL; EINEXACT for GOAC_MIXED when a shifted charge is not exact
+ * in bfloat16. */
+goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
+                          goac_precision prec, double* E_dev);
+
+/* The k lowest configurations among P candidates (Methodology: the n lowest
+ * structures are the output): FP64 energies ordered by (E, index).
+ *   idx_dev : k int64 output; E_dev : k FP64 output (k <= P). */
+goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t* occ_dev, int32_t k,
+                           int64_t* idx_dev, double* E_dev);
+
+/* ---------------------------------------------------------------- Monte Carlo (a3-a5) */
+
+/* A set of C Metropolis swap chains on one problem (SI, "Monte Carlo" and
+ * "Simulated annealing"). Each chain keeps its occupation, the per-sublattice
+ * position lists sorted by species at creation (perm), the field phi = V_mm q +
+ * h, its energy E, its trial counter t, counts, the best energy seen and its
+ * occupation.
+ *   occ_dev   : C x n start occupations; each must keep the problem's
+ *               composition (EINVAL otherwise; the check synchronises)
+ *   prec      : GOAC_FP64 (FP64 phi) or GOAC_MIXED (FP32 phi)
+ *   chain_base: id of chain 0 in the Philox counters
+ *   instance  : instance id in the Philox counters */
+goac_status goac_chains_create(goac_problem* pb, int64_t C, const uint8_t* occ_dev,
+                               goac_precision prec, uint32_t chain_base, uint32_t instance,
+                               goac_chains** out);
+void goac_chains_destroy(goac_chains* ch);
+
+/* Many independent problems in one set of chains: instance i has
+ * chains_per_instance[i] chains; chain ids restart at 0 for every instance and
+ * the instance id is i. occ_dev holds the start occupations of all chains,
+ * instance after instance, each row n_i long. Problems must share the context.
+ * The sweep runs every chain of every instance in one persistent launch. */
+goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_t n_instances,
+                                     const int64_t* chains_per_instance, const uint8_t* occ_dev,
+                                     goac_precision prec, goac_chains** out);
+
+#define GOAC_MC_TRACE_HASH 1u   /* accumulate the per-trial trajectory hash */
+
+/* Parameters of one sweep. kT_host is a table of n_rows x n_blocks kT values
+ * (eV); chain c at trial t uses row r_c (the chain set's temperature row, 0
+ * unless set by goac_chains_set_rows or goac_remc_exchange) and column
+ * min(t / block_len, n_blocks - 1). */
+typedef struct {
+    uint64_t seed;
+    uint64_t n_trials;          /* trials added to every chain                     */
+    const double* kT_host;
+    int32_t n_rows;
+    int32_t n_blocks;
+    uint64_t block_len;
+    int32_t reanchor_every;     /* MIXED: re-anchor after this many field updates  */
+    uint32_t flags;             /* GOAC_MC_TRACE_HASH                              */
+    int32_t variant;            /* 0: automatic; 64 or 256: threads per chain      */
+    int32_t reserved;
+} goac_mc_params;
+
+/* Set the temperature row of every chain (rows_host: C int32 >= 0). */
+goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows_host);
+
+/* Advance every chain by n_trials trials. Trial t of chain c (instance i):
+ *   (r0,r1,r2,r3) = Philox4x32-10(counter (t_lo, t_hi, c, i << 8 | 1), key seed)
+ *   a = mobile position (r0 M) >> 32 (species a, sublattice s), cnt = P_s -
+ *   n_{s,a}; partner = perm_s[k < off_{s,a} ? k : k + n_{s,a}], k = (r1 cnt) >> 32;
+ *   d = q_b - q_a; dE = d (phi_i - phi_j) + d^2/2 (V_ii + V_jj - 2 V_ij);
+ *   u = ((r2:r3 >> 12) + 1/2) 2^-52; accept iff dE <= 0 or u < exp(-dE/kT).
+ * On acceptance the two positions swap and phi_k += d (V_ik - V_jk) for every
+ * mobile k. Chains resume where the previous sweep stopped.
+ * GOAC_MIXED decides from the FP32 field only when the FP64 decision cannot
+ * differ within a rigorous error bound; otherwise it recomputes phi_i and phi_j
+ * in FP64. The field is re-anchored in FP64 between chunks once a chain has made
+ * reanchor_every field updates. Returns GOAC_EDRIFT if the field left its
+ * bound (a NaN or an overflow). */
+goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* params);
+
+typedef struct {
+    uint64_t t;          /* trials done                                         */
+    uint64_t accepts;    /* accepted trials                                     */
+    uint64_t updates;    /* accepted trials that changed the field (d != 0)     */
+    uint64_t hash;       /* sum over trials of the per-trial hash (TRACE_HASH)  */
+    uint64_t fallbacks;  /* MIXED: trials decided by the FP64 recompute         */
+    uint64_t anchors;    /* MIXED: FP64 re-anchors                              */
+    double E;            /* energy of the current occupation                    */
+    double best_E;       /* lowest energy seen                                  */
+    int32_t status;      /* 0, or 1 if the FP32 field left its bound (MIXED)    */
+    int32_t row;         /* temperature row                                     */
+} goac_chain_stats;
+
+/* Copy chain results to caller buffers (any pointer may be NULL):
+ *   occ_dev, best_occ_dev : C x n; stats_dev : C goac_chain_stats (device). */
+goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_occ_dev,
+                               goac_chain_stats* stats_dev);
+
+/* Replica exchange (SI, "Replica Exchange Monte Carlo"): chains form
+ * consecutive groups of R replicas on the ladder kT_host[0..R) (ascending). At
+ * exchange step x, neighbours (k, k+1), k = x mod 2, x mod 2 + 2, ..., swap
+ * temperatures with probability min(1, exp((E_k - E_k+1)(1/kT_k - 1/kT_k+1))),
+ * E_k the energy of the chain at temperature k and u = ((r0:r1 >> 12) + 1/2)
+ * 2^-52 from Philox at counter (k, x_lo, x_hi, group << 8 | 6), key seed.
+ * Configurations stay with their chains; the chains' temperature rows move.
+ *   slot_dev : (C / R) x R int32, the chain (index within its group) at each
+ *              temperature, in/out
+ *   acc_dev  : (C / R) x R uint8 accepted flags per lower index k (may be NULL)
+ * Sweeps after an exchange run chain c at row = its temperature index. */
+goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host, uint64_t x,
+                               uint64_t seed, int32_t* slot_dev, uint8_t* acc_dev);
+
+/* ---------------------------------------------------------------- GA (a6) */
+
+typedef struct {
+    uint64_t seed;
+    uint32_t generation;
+    int32_t n_elite;
+    double p_mut;
+} goac_ga_params;
+
+/* One generation of the genetic algorithm (SI, "Genetic Algorithm"):
+ *   elitism   : children 0..n_elite-1 are the parents ordered by (E, index)
+ *   roulette  : weights w_p = E_max - E_p rounded to integer multiples of 2^-30
+ *               eV and summed exactly; parent = the smallest p whose cumulative
+ *               weight exceeds floor(x W / 2^64), x a 64-bit Philox draw at
+ *               counter (c, g, 0, 3) (uniform choice when W = 0)
+ *   crossover : the canonical swap path from parent A to parent B is walked and
+ *               each of its swaps enters the child with probability 1/2 (top bit
+ *               of Philox at counter (position, c, g, 4))
+ *   mutation  : with probability p_mut one valid swap (Philox at (c, g, 1, 5))
+ *   pop_in_dev : P x n; E_in_dev : P FP64; pop_out_dev : P x n (not aliasing pop_in).
+ * Errors: EINVAL, also if (E_max - E_min) 2^30 P exceeds 2^62. */
+goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
+                               const double* E_in_dev, const goac_ga_params* params,
+                               uint8_t* pop_out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOAC_H */

@@ -1,0 +1,251 @@
+// Shared declarations of the gfx950 library: device structs, the counter-based
+// RNG, the trajectory hash and launch helpers. Host and device code of the
+// library include this; the CPU oracle does not.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/goac.h"
+
+namespace goac {
+
+constexpr int kMaxSub = 16;       // sublattices per problem
+constexpr int kMaxSpecies = 32;   // species ids per problem
+constexpr int kPad = 64;          // mobile dimension padded to a multiple of this
+
+enum : uint32_t { TAG_MC = 1, TAG_INIT = 2, TAG_SEL = 3, TAG_X = 4, TAG_MUT = 5, TAG_REMC = 6 };
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64 products of counter words 0 and 2 with fixed multipliers, the high
+// halves xor-ed with the other counter words and the round key, which advances by
+// the Weyl constants after every round.
+struct u32x4 { uint32_t x, y, z, w; };
+
+__host__ __device__ inline u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint64_t seed) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// uniform on (0, 1): 52 high bits of hi:lo plus one half, times 2^-52 (exact)
+__host__ __device__ inline double unit_open(uint32_t hi, uint32_t lo) {
+    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+
+// multiply-shift index in [0, n)
+__host__ __device__ inline uint32_t mulshift(uint32_t r, uint32_t n) {
+    return (uint32_t)(((uint64_t)r * n) >> 32);
+}
+
+// splitmix64 output function (Steele, Lea, Flood, OOPSLA'14)
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// per-trial term of the order-independent trajectory hash (sum mod 2^64)
+__host__ __device__ inline uint64_t trial_hash(uint64_t t, uint32_t i, uint32_t j, uint32_t acc) {
+    return splitmix64(splitmix64(t) ^ (((uint64_t)i << 33) | ((uint64_t)j << 1) | (acc & 1u)));
+}
+
+// ------------------------------------------------------------------ device structs
+
+// Sublattice tables of a problem, laid out as int32 words:
+//   [0]            S
+//   [1]            E
+//   [2 .. 2+S)     P_s  (positions of sublattice s)
+//   [.. + S)       start of sublattice s in the concatenated position lists
+//   [.. + S*E)     n_{s,e} (ions of species e on sublattice s)
+//   [.. + S*E)     off_{s,e} = sum_{e' < e} n_{s,e'}
+__host__ __device__ inline int tab_words(int S, int E) { return 2 + 2 * S + 2 * S * E; }
+
+struct ProblemDev {
+    int64_t n;
+    int32_t M, Mp, S, E;
+    int32_t* mob;        // M: site index of mobile position k (ascending)
+    uint8_t* msub;       // Mp: sublattice of position k (0 beyond M)
+    uint8_t* ref_occ;    // n: the problem's occupation (fixed-site species)
+    double* V64;         // M x Mp: mobile block, FP64 (zero beyond M)
+    float* V32;          // M x Mp: FP32 rounding of V64
+    __hip_bfloat16* Vhi; // Mp x Mp: bf16(V)
+    __hip_bfloat16* Vlo; // Mp x Mp: bf16(V - Vhi)
+    double* diag;        // M
+    float* rowmax;       // M: max_k |V_ik|, rounded up
+    double* rowabs;      // M: sum_k |V_ik|
+    double* h;           // Mp: field of the fixed ions
+    double* ht;          // Mp: h + V_mm c
+    double* phibar;      // S: mean field of each sublattice at the reference occupation
+    double* charge;      // E
+    double* dq;          // S x E: charge[e] - c_s
+    int32_t* tab;        // sublattice tables (tab_words)
+    double E_ff;         // energy of the fixed ions
+    double E_t;          // E_ff + c^T h + 1/2 c^T V_mm c
+    double qmax;         // max |charge|
+    int mixed_exact;
+};
+
+// Per-chain scalars of the Monte Carlo state (device array, one per chain).
+struct ChainScalars {
+    uint64_t t, accepts, updates, hash, fallbacks, anchors;
+    double E, best_E;
+    double eps;              // bound on |phi32 - phi| (MIXED)
+    float phibound;          // power-of-two bound on |phi| (MIXED)
+    uint32_t since_anchor;   // field updates since the last FP64 anchor
+    int32_t inst;            // instance index
+    uint32_t chain_id;       // chain id in the Philox counters
+    int32_t row;             // temperature row
+    int32_t status;          // 0, or 1 once the field left its bound
+    int64_t off;             // element offset of the chain's arrays
+};
+
+// Per-instance view the Monte Carlo kernels read.
+struct McInst {
+    const double* V64;
+    const float* V32;
+    const double* diag;
+    const float* rowmax;
+    const double* h;
+    const double* phibar;   // S: offset of the stored FP32 field per sublattice
+    const uint8_t* msub;
+    const int32_t* tab;
+    const double* charge;
+    double E_ff;
+    int32_t M, Mp, S, E;
+    uint32_t instance;      // instance id in the Philox counters
+    int32_t pad_;
+};
+
+}  // namespace goac
+
+// ------------------------------------------------------------------ host objects
+struct goac_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 256;
+    std::string err;
+    void* ws = nullptr;     // scratch, grown on demand
+    size_t ws_size = 0;
+};
+
+struct goac_problem {
+    goac_ctx* ctx = nullptr;
+    goac::ProblemDev d{};
+    std::vector<int32_t> tab_host;  // tables on the host
+    std::vector<int32_t> mob_host;
+    std::vector<double> charge_host;
+    std::vector<double> shift_host;  // c_s
+    int32_t* spos = nullptr;         // M: positions of each sublattice, ascending, concatenated
+    int32_t* spos_inv = nullptr;     // M: index of position k in spos
+    int32_t* fixed_idx = nullptr;    // fixed sites
+    int32_t n_fixed = 0;
+};
+
+struct goac_chains {
+    goac_ctx* ctx = nullptr;
+    std::vector<goac_problem*> pbs;   // one per instance
+    goac_precision prec = GOAC_FP64;
+    int64_t C = 0;                    // chains
+    int64_t total = 0;                // elements of the per-chain arrays
+    int32_t max_Mp = 0;
+    int32_t max_S = 1, max_E = 1;
+    goac::ChainScalars* sc = nullptr; // C
+    goac::McInst* insts = nullptr;    // instances
+    void* phi = nullptr;              // float or double, total
+    uint8_t* occ = nullptr;           // total
+    uint16_t* perm = nullptr;         // total
+    uint8_t* best = nullptr;          // total
+    int32_t* order = nullptr;         // C, longest chains first
+    int32_t* queue = nullptr;         // work counter of the persistent sweep
+    int32_t* due = nullptr;           // C + 1: chains due for re-anchoring
+    double* kT = nullptr;             // device kT table
+    size_t kT_cap = 0;
+    int64_t* d_offs = nullptr;        // C element offsets (device)
+    int32_t max_tab = 0;              // int32 words of the largest table
+    int32_t max_row = 0;              // largest temperature row in use
+    std::vector<int64_t> offs;        // element offsets per chain (host)
+    std::vector<int32_t> inst_of;     // instance of each chain (host)
+    std::vector<uint32_t> chain_id;   // Philox chain id of each chain
+    std::vector<uint32_t> inst_id;    // Philox instance id of each instance
+    std::vector<int64_t> count;       // chains per instance
+    std::vector<int64_t> first_chain; // first chain of each instance
+    std::vector<int64_t> occ_row_off; // byte offset of an instance's first occupation row
+};
+
+// ------------------------------------------------------------------ error helpers
+namespace goac {
+
+inline goac_status fail(goac_ctx* ctx, goac_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define GOAC_HIP(ctx, expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::goac::fail((ctx), e_ == hipErrorOutOfMemory ? GOAC_ENOMEM : GOAC_EHIP, \
+                                std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define GOAC_CHECK_LAUNCH(ctx) GOAC_HIP(ctx, hipGetLastError())
+
+// Monte Carlo launch arguments
+struct McArgs {
+    const McInst* insts;
+    ChainScalars* sc;
+    void* phi;
+    uint8_t* occ;
+    uint16_t* perm;
+    uint8_t* best;
+    const int32_t* order;
+    int32_t* queue;
+    int32_t n_items;
+    int32_t n_blocks;
+    const double* kT;      // rows x n_blocks
+    uint64_t block_len;
+    uint64_t n_trials;
+    uint64_t seed;
+    int32_t reanchor_every;
+    int32_t lds_phi_bytes; // bytes reserved for phi (Mp_max * sizeof)
+    int32_t Mp_max;
+    int32_t tab_max;       // int32 words reserved for tables
+};
+
+goac_status mc_launch(goac_ctx* ctx, const McArgs& a, bool mixed, bool trace, int wg, size_t lds, int grid);
+goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
+                      const int32_t* mob, const double* charge, double* Q);
+
+// scratch memory of a context (grown, never shrunk)
+goac_status workspace(goac_ctx* ctx, size_t bytes, void** out = nullptr);
+
+// kernels shared across translation units
+goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                     const int32_t* M_dev);
+
+}  // namespace goac

@@ -1,0 +1,214 @@
+// Ewald pair matrix on gfx950 (Methodology, "Cluster Expansion of Coulomb
+// Energy": periodic point-charge energies by Ewald summation).
+//
+//   V_ij = k_e [ sum_{m: 0 < |r+mA| < rc} erfc(a|r+mA|)/|r+mA|            (real)
+//              + (4 pi/W) sum_{G != 0} e^{-G^2/4a^2}/G^2 cos(G.r)           (reciprocal)
+//              - pi/(W a^2) ] - delta_ij k_e 2a/sqrt(pi),   r = r_j - r_i.
+//
+// Real space: one thread per entry loops over the lattice translations that can
+// bring an image within rc (FP64 VALU, erfc). Reciprocal space: G and -G pair up,
+// so the sum over the half space with weight w_G = 2 (4 pi/W) e^{-G^2/4a^2}/G^2 is
+// sum_G w_G [cos(G.r_i) cos(G.r_j) + sin(G.r_i) sin(G.r_j)] = (T T^T)_ij with
+// T_{i,2g} = sqrt(k_e w_g) cos(G_g.r_i), T_{i,2g+1} = sqrt(k_e w_g) sin(G_g.r_i):
+// an FP64 matrix-core product added onto the real-space part.
+#include <cmath>
+
+#include "common.h"
+
+namespace goac {
+
+namespace {
+constexpr double kPi = 3.14159265358979323846;
+
+struct Cell {
+    double A[3][3];
+    double B[3][3];
+    double vol;
+};
+
+bool cell_setup(const double* lat, Cell& c) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c.A[i][j] = lat[3 * i + j];
+    double cr[3][3];
+    for (int i = 0; i < 3; ++i) {
+        const double* u = c.A[(i + 1) % 3];
+        const double* v = c.A[(i + 2) % 3];
+        cr[i][0] = u[1] * v[2] - u[2] * v[1];
+        cr[i][1] = u[2] * v[0] - u[0] * v[2];
+        cr[i][2] = u[0] * v[1] - u[1] * v[0];
+    }
+    const double det = c.A[0][0] * cr[0][0] + c.A[0][1] * cr[0][1] + c.A[0][2] * cr[0][2];
+    if (!(std::fabs(det) > 1e-12)) return false;
+    c.vol = std::fabs(det);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c.B[i][j] = 2.0 * kPi * cr[i][j] / det;
+    return true;
+}
+
+double norm3(const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+}  // namespace
+
+// Real-space part plus the constant terms. Positions arrive reduced to
+// fractional coordinates in [0, 1); r = r_j - r_i is folded to (-1/2, 1/2] per
+// axis before the translation loop.
+__global__ void k_ewald_real(int64_t n, const double* __restrict__ frac, const double* __restrict__ A9,
+                             const double* __restrict__ trans, int32_t n_trans, double alpha, double rcut,
+                             double ke, double cst, double self, double* __restrict__ V) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= n) return;
+    double f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double x = frac[3 * j + d] - frac[3 * i + d];
+        x -= rint(x);
+        f[d] = x;
+    }
+    double r[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) r[d] = f[0] * A9[d] + f[1] * A9[3 + d] + f[2] * A9[6 + d];
+    const double rc2 = rcut * rcut;
+    double s = 0.0;
+    for (int m = 0; m < n_trans; ++m) {
+        const double x = r[0] + trans[3 * m], y = r[1] + trans[3 * m + 1], z = r[2] + trans[3 * m + 2];
+        const double d2 = x * x + y * y + z * z;
+        if (d2 < rc2 && d2 > 0.0) {
+            const double dd = sqrt(d2);
+            s += erfc(alpha * dd) / dd;
+        }
+    }
+    double v = ke * s + cst;
+    if (i == j) v -= self;
+    V[i * n + j] = v;
+}
+
+// T[i][2g] = s_g cos(G_g.r_i), T[i][2g+1] = s_g sin(G_g.r_i), zero padding to ld
+__global__ void k_ewald_table(int64_t n, int32_t K, int32_t ld, const double* __restrict__ pos,
+                              const double* __restrict__ G, double* __restrict__ T) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * (int64_t)ld / 2) return;
+    const int64_t i = idx / (ld / 2);
+    const int g = (int)(idx - i * (ld / 2));
+    double c = 0.0, s = 0.0;
+    if (g < K) {
+        const double gr = G[4 * g] * pos[3 * i] + G[4 * g + 1] * pos[3 * i + 1] + G[4 * g + 2] * pos[3 * i + 2];
+        const double w = G[4 * g + 3];
+        sincos(gr, &s, &c);
+        c *= w;
+        s *= w;
+    }
+    T[i * ld + 2 * g] = c;
+    T[i * ld + 2 * g + 1] = s;
+}
+
+// CODATA 2018: e = 1.602176634e-19 C, eps0 = 8.8541878128e-12 F/m -> eV A
+static double coulomb_constant() { return 1.602176634e-19 / (4.0 * kPi * 8.8541878128e-12) * 1e10; }
+
+goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const double* pos, const goac_ewald_params* prm,
+                        double* V) {
+    Cell c;
+    if (!cell_setup(lat, c)) return fail(ctx, GOAC_EINVAL, "build_ewald: singular lattice");
+    double alpha = prm ? prm->alpha : 0.0, rcut = prm ? prm->rcut : 0.0;
+    int kmax = prm ? prm->kmax : 0;
+    if (!(alpha > 0.0)) alpha = 5.0 / std::cbrt(c.vol);
+    if (!(rcut > 0.0)) rcut = 6.0 / alpha;
+    if (kmax <= 0) {
+        double amax = 0.0;
+        for (int i = 0; i < 3; ++i) amax = std::fmax(amax, norm3(c.A[i]));
+        kmax = (int)std::ceil(12.0 * alpha * amax / (2.0 * kPi));
+    }
+    if (kmax > 200) return fail(ctx, GOAC_EINVAL, "build_ewald: reciprocal index radius above 200");
+    const double ke = coulomb_constant();
+
+    // fractional coordinates in [0, 1)
+    // inverse of A (rows a_i): f = r A^-1, A^-1 = B^T / (2 pi)
+    std::vector<double> frac(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double* r = pos + 3 * i;
+            double f = (r[0] * c.B[d][0] + r[1] * c.B[d][1] + r[2] * c.B[d][2]) / (2.0 * kPi);
+            f -= std::floor(f);
+            frac[3 * i + d] = f;
+        }
+    // lattice translations whose images of a folded r (|f_d| <= 1/2) can lie within rcut:
+    // (|m_d| - 1/2) times the plane spacing of axis d must stay below rcut
+    std::vector<double> trans;
+    int nm[3];
+    double spacing[3];
+    for (int d = 0; d < 3; ++d) {
+        spacing[d] = 2.0 * kPi / norm3(c.B[d]);
+        nm[d] = (int)std::ceil(rcut / spacing[d] + 0.5);
+    }
+    for (int a = -nm[0]; a <= nm[0]; ++a)
+        for (int b = -nm[1]; b <= nm[1]; ++b)
+            for (int e = -nm[2]; e <= nm[2]; ++e) {
+                const int m[3] = {a, b, e};
+                bool skip = false;
+                for (int d = 0; d < 3; ++d)
+                    if ((std::abs(m[d]) - 0.5) * spacing[d] >= rcut) skip = true;
+                if (skip) continue;
+                for (int k = 0; k < 3; ++k) trans.push_back(a * c.A[0][k] + b * c.A[1][k] + e * c.A[2][k]);
+            }
+    // half-space reciprocal vectors (first non-zero index positive) with weights
+    std::vector<double> G;
+    for (int a = -kmax; a <= kmax; ++a)
+        for (int b = -kmax; b <= kmax; ++b)
+            for (int e = -kmax; e <= kmax; ++e) {
+                if (a * a + b * b + e * e > kmax * kmax) continue;
+                if (!(a > 0 || (a == 0 && b > 0) || (a == 0 && b == 0 && e > 0))) continue;
+                double g[3];
+                for (int k = 0; k < 3; ++k) g[k] = a * c.B[0][k] + b * c.B[1][k] + e * c.B[2][k];
+                const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+                const double w = 2.0 * (4.0 * kPi / c.vol) * std::exp(-g2 / (4.0 * alpha * alpha)) / g2;
+                G.insert(G.end(), {g[0], g[1], g[2], std::sqrt(ke * w)});
+            }
+    const int32_t K = (int32_t)(G.size() / 4);
+    const int32_t ld = (int32_t)round_up(2 * (int64_t)std::max(K, 1), 16);
+
+    const size_t b_frac = round_up(frac.size() * 8, 256), b_pos = round_up(3 * n * 8, 256);
+    const size_t b_tr = round_up(trans.size() * 8 + 8, 256), b_G = round_up(G.size() * 8 + 8, 256);
+    const size_t b_A = 256, b_T = (size_t)n * ld * 8;
+    void* ws = nullptr;
+    goac_status st = workspace(ctx, b_frac + b_pos + b_tr + b_G + b_A + b_T, &ws);
+    if (st != GOAC_OK) return st;
+    char* p = (char*)ws;
+    double* d_frac = (double*)p; p += b_frac;
+    double* d_pos = (double*)p; p += b_pos;
+    double* d_tr = (double*)p; p += b_tr;
+    double* d_G = (double*)p; p += b_G;
+    double* d_A = (double*)p; p += b_A;
+    double* d_T = (double*)p;
+    // folded Cartesian positions for the tables (exact phase equivalence mod 2 pi)
+    std::vector<double> cpos(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k)
+            cpos[3 * i + k] = frac[3 * i] * c.A[0][k] + frac[3 * i + 1] * c.A[1][k] + frac[3 * i + 2] * c.A[2][k];
+    GOAC_HIP(ctx, hipMemcpyAsync(d_frac, frac.data(), frac.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    GOAC_HIP(ctx, hipMemcpyAsync(d_pos, cpos.data(), cpos.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    if (!trans.empty())
+        GOAC_HIP(ctx, hipMemcpyAsync(d_tr, trans.data(), trans.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    if (!G.empty()) GOAC_HIP(ctx, hipMemcpyAsync(d_G, G.data(), G.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    GOAC_HIP(ctx, hipMemcpyAsync(d_A, &c.A[0][0], 9 * 8, hipMemcpyHostToDevice, ctx->stream));
+    const double cst = -ke * kPi / (c.vol * alpha * alpha);
+    const double self = ke * 2.0 * alpha / std::sqrt(kPi);
+    {
+        dim3 grid((unsigned)((n + 127) / 128), (unsigned)n);
+        hipLaunchKernelGGL(k_ewald_real, grid, dim3(128), 0, ctx->stream, n, d_frac, d_A, d_tr,
+                           (int32_t)(trans.size() / 3), alpha, rcut, ke, cst, self, V);
+        GOAC_CHECK_LAUNCH(ctx);
+    }
+    if (K > 0) {
+        const int64_t tot = n * (int64_t)ld / 2;
+        hipLaunchKernelGGL(k_ewald_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, n, K, ld,
+                           d_pos, d_G, d_T);
+        GOAC_CHECK_LAUNCH(ctx);
+        st = dgemm_nt(ctx, n, n, ld, d_T, ld, d_T, ld, V, n, 1.0, 1.0, nullptr);
+        if (st != GOAC_OK) return st;
+    }
+    // the workspace may be reused by the next call on this stream; host vectors are
+    // released here, so wait for the copies to complete
+    GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GOAC_OK;
+}
+
+}  // namespace goac

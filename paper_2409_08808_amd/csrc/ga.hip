@@ -1,0 +1,267 @@
+// Genetic-algorithm generation, random starts and top-k selection on gfx950
+// (SI, "Genetic Algorithm" and "Random"; Methodology: output of the n lowest
+// configurations).
+#include "common.h"
+
+namespace goac {
+
+// ------------------------------------------------------------------ random starts
+// One workgroup per (chain, sublattice): the canonical species sequence of the
+// sublattice is shuffled by Fisher-Yates. The draws m_k = (r_k (k+1)) >> 32 are
+// independent (counter-based), so the lanes compute them in parallel; the swaps,
+// which are order-dependent, run on one lane.
+__global__ void k_init(int64_t n, int32_t S, int32_t E, const int32_t* __restrict__ tab,
+                       const int32_t* __restrict__ spos, const int32_t* __restrict__ mob,
+                       const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ,
+                       uint64_t seed, uint32_t chain_base, uint32_t instance, uint8_t* __restrict__ occ) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int64_t c = blockIdx.x / S;
+    const int s = (int)(blockIdx.x - c * S);
+    const int32_t* subsize = tab + 2;
+    const int32_t* suboff = subsize + S;
+    const int32_t* cnt = suboff + S;
+    const int32_t* offs = cnt + S * E;
+    const int Ps = subsize[s];
+    uint8_t* arr = lds;
+    uint16_t* mk = reinterpret_cast<uint16_t*>(lds + round_up(Ps, 16));
+    const uint32_t chain = chain_base + (uint32_t)c;
+    for (int x = threadIdx.x; x < Ps; x += blockDim.x) {
+        int e = 0;
+        while (!(x < offs[s * E + e] + cnt[s * E + e])) ++e;
+        arr[x] = (uint8_t)e;
+        if (x >= 1) {
+            const u32x4 r = philox((uint32_t)x, (uint32_t)s, chain, (instance << 8) | TAG_INIT, seed);
+            mk[x] = (uint16_t)mulshift(r.x, (uint32_t)(x + 1));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = Ps - 1; k >= 1; --k) {
+            const int m = mk[k];
+            const uint8_t t = arr[k];
+            arr[k] = arr[m];
+            arr[m] = t;
+        }
+    __syncthreads();
+    uint8_t* row = occ + c * n;
+    for (int x = threadIdx.x; x < Ps; x += blockDim.x) row[mob[spos[suboff[s] + x]]] = arr[x];
+    if (s == 0)
+        for (int f = threadIdx.x; f < n_fixed; f += blockDim.x) row[fixed_idx[f]] = ref_occ[fixed_idx[f]];
+}
+
+// ------------------------------------------------------------------ GA: selection tables
+// One workgroup: E_max, integer roulette weights round((E_max - E_p) 2^30) and
+// their inclusive prefix sums (exact, so the order of the additions does not
+// matter), and the n_elite smallest (E, index) pairs by rank counting.
+__global__ __launch_bounds__(1024) void k_ga_prep(int64_t P, const double* __restrict__ E, int32_t n_elite,
+                                                  uint64_t* __restrict__ cum, int32_t* __restrict__ elite,
+                                                  int32_t* __restrict__ err) {
+    __shared__ double s_red[1024];
+    __shared__ uint64_t s_tot[1024];
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    double mx = -INFINITY;
+    for (int64_t p = tid; p < P; p += nt) mx = fmax(mx, E[p]);
+    s_red[tid] = mx;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (tid < w) s_red[tid] = fmax(s_red[tid], s_red[tid + w]);
+        __syncthreads();
+    }
+    const double emax = s_red[0];
+    const double lim = 0x1p62 / (double)P;
+    // contiguous chunk per thread
+    const int64_t chunk = (P + nt - 1) / nt;
+    const int64_t lo = tid * chunk, hi = lo + chunk < P ? lo + chunk : P;
+    uint64_t run = 0;
+    bool bad = false;
+    for (int64_t p = lo; p < hi; ++p) {
+        const double w = (emax - E[p]) * 0x1p30;
+        if (!(w < lim)) bad = true;
+        run += bad ? 0 : (uint64_t)(w + 0.5);
+        cum[p] = run;
+    }
+    if (bad) atomicOr(err, 1);
+    s_tot[tid] = run;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t acc = 0;
+        for (int q = 0; q < nt; ++q) {
+            const uint64_t v = s_tot[q];
+            s_tot[q] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    const uint64_t base = s_tot[tid];
+    for (int64_t p = lo; p < hi; ++p) cum[p] += base;
+    for (int64_t p = tid; p < P; p += nt) {
+        const double ep = E[p];
+        int64_t rank = 0;
+        for (int64_t q = 0; q < P && rank < n_elite; ++q) {
+            const double eq = E[q];
+            rank += (eq < ep || (eq == ep && q < p)) ? 1 : 0;
+        }
+        if (rank < n_elite) elite[rank] = (int32_t)p;
+    }
+}
+
+__device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// smallest p with cum[p] > target
+__device__ inline int64_t upper_bound_u64(const uint64_t* cum, int64_t P, uint64_t target) {
+    int64_t lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cum[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// first position >= from (in the sublattice's ascending list [0, len)) whose
+// predicate holds, scanning 64 at a time with a ballot; len if none
+template <typename Pred>
+__device__ inline int wave_find(int from, int len, Pred pred) {
+    const int lane = threadIdx.x & 63;
+    for (int base = from; base < len; base += 64) {
+        const int x = base + lane;
+        const bool hit = x < len && pred(x);
+        const uint64_t m = __ballot(hit);
+        if (m) return base + (int)__ffsll((long long)m) - 1;
+    }
+    return len;
+}
+
+// ------------------------------------------------------------------ GA: one child per wavefront
+__global__ __launch_bounds__(64) void k_ga_child(
+    int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
+    const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob, const int32_t* __restrict__ fixed_idx, int32_t n_fixed,
+    const uint8_t* __restrict__ ref_occ, int64_t P, const uint8_t* __restrict__ pop_in,
+    const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite, int32_t n_elite, uint64_t seed,
+    uint32_t g, double p_mut, uint8_t* __restrict__ pop_out) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    uint8_t* out = pop_out + c * n;
+    if (c < n_elite) {
+        int64_t ep = elite[c];
+        if (ep < 0 || ep >= P) ep = 0;   // unranked (NaN energies); the call reports the error
+        const uint8_t* src = pop_in + ep * n;
+        for (int64_t x = lane; x < n; x += 64) out[x] = src[x];
+        return;
+    }
+    const int32_t* subsize = tab + 2;
+    const int32_t* suboff = subsize + S;
+    const int32_t* cnt = suboff + S;
+    const int32_t* offs = cnt + S * E;
+    // parents
+    const u32x4 r = philox((uint32_t)c, g, 0u, TAG_SEL, seed);
+    const uint64_t xa = ((uint64_t)r.x << 32) | r.y, xb = ((uint64_t)r.z << 32) | r.w;
+    const uint64_t W = cum[P - 1];
+    int64_t pa, pb;
+    if (W == 0) {
+        pa = (int64_t)mulhi64(xa, (uint64_t)P);
+        pb = (int64_t)mulhi64(xb, (uint64_t)P);
+    } else {
+        pa = upper_bound_u64(cum, P, mulhi64(xa, W));
+        pb = upper_bound_u64(cum, P, mulhi64(xb, W));
+    }
+    // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent B)
+    const int Mr = (int)round_up(M, 16);
+    uint8_t* ch = lds;
+    uint8_t* rf = lds + Mr;
+    uint8_t* bb = lds + 2 * Mr;
+    const uint8_t* A = pop_in + pa * n;
+    const uint8_t* B = pop_in + pb * n;
+    for (int x = lane; x < M; x += 64) {
+        const int site = mob[spos[x]];
+        const uint8_t a = A[site];
+        ch[x] = a;
+        rf[x] = a;
+        bb[x] = B[site];
+    }
+    __syncthreads();
+    // crossover: walk the canonical swap path from A to B (positions ascending
+    // within each sublattice); each path swap enters the child with probability 1/2
+    for (int s = 0; s < S; ++s) {
+        const int base = suboff[s], len = subsize[s];
+        uint8_t* rs = rf + base;
+        uint8_t* cs = ch + base;
+        const uint8_t* bs = bb + base;
+        int p = 0;
+        for (;;) {
+            p = wave_find(p, len, [&](int x) { return rs[x] != bs[x]; });
+            if (p >= len) break;
+            const uint8_t want = bs[p];
+            const int q = wave_find(p + 1, len, [&](int x) { return rs[x] == want && rs[x] != bs[x]; });
+            if (q >= len) break;  // cannot happen: ref and B share the composition
+            if (lane == 0) {
+                const uint8_t t = rs[p]; rs[p] = rs[q]; rs[q] = t;
+                const u32x4 rx = philox((uint32_t)spos[base + p], (uint32_t)c, g, TAG_X, seed);
+                if (rx.x >> 31) { const uint8_t t2 = cs[p]; cs[p] = cs[q]; cs[q] = t2; }
+            }
+            __syncthreads();
+            ++p;
+        }
+    }
+    // mutation: one valid swap with probability p_mut
+    const u32x4 rm = philox((uint32_t)c, g, 1u, TAG_MUT, seed);
+    if (M > 0 && unit_open(rm.z, rm.w) < p_mut) {
+        const int im = (int)mulshift(rm.x, (uint32_t)M);
+        const int s = msub[im];
+        const int base = suboff[s];
+        const int px = spos_inv[im] - base;
+        const uint8_t a = ch[base + px];
+        const int na = cnt[s * E + a];
+        const int cn = subsize[s] - na;
+        if (cn > 0) {
+            const int k = (int)mulshift(rm.y, (uint32_t)cn);
+            const int idx = k < offs[s * E + a] ? k : k + na;
+            int e = 0;
+            while (!(idx < offs[s * E + e] + cnt[s * E + e])) ++e;
+            int rank = idx - offs[s * E + e];
+            // rank-th position of species e, ascending
+            int pos = -1;
+            const int len = subsize[s];
+            for (int b0 = 0; b0 < len && pos < 0; b0 += 64) {
+                const int x = b0 + lane;
+                const bool hit = x < len && ch[base + x] == e;
+                const uint64_t m = __ballot(hit);
+                const int pc = __popcll(m);
+                if (rank < pc) {
+                    uint64_t mm = m;
+                    for (int z = 0; z < rank; ++z) mm &= mm - 1;
+                    pos = b0 + (int)__ffsll((long long)mm) - 1;
+                } else {
+                    rank -= pc;
+                }
+            }
+            if (lane == 0 && pos >= 0) {
+                const uint8_t t = ch[base + px]; ch[base + px] = ch[base + pos]; ch[base + pos] = t;
+            }
+            __syncthreads();
+        }
+    }
+    for (int x = lane; x < M; x += 64) out[mob[spos[x]]] = ch[x];
+    for (int f = lane; f < n_fixed; f += 64) out[fixed_idx[f]] = ref_occ[fixed_idx[f]];
+}
+
+// ------------------------------------------------------------------ top-k by rank counting
+__global__ void k_topk_select(int64_t P, int32_t k, const double* __restrict__ E, int64_t* __restrict__ idx,
+                              double* __restrict__ Eout) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double ep = E[p];
+    int64_t rank = 0;
+    for (int64_t q = 0; q < P && rank < k; ++q) {
+        const double eq = E[q];
+        rank += (eq < ep || (eq == ep && q < p)) ? 1 : 0;
+    }
+    if (rank < k) {
+        idx[rank] = p;
+        Eout[rank] = ep;
+    }
+}
+
+}  // namespace goac

@@ -1,0 +1,291 @@
+// Matrix-core products of the library (gfx950 MFMA):
+//   dgemm_nt        C = alpha A B^T + beta C in FP64 (v_mfma_f64_16x16x4f64): the
+//                   reciprocal-space Ewald sum, FP64 population energies and the
+//                   FP64 re-anchoring of the Monte Carlo field.
+//   k_pop_bf16      Phi = dQ (V_hi + V_lo) with bf16 inputs and FP32 accumulation
+//                   (v_mfma_f32_32x32x16_bf16) and a fused FP64 row-dot epilogue:
+//                   the mixed-precision population energies.
+#include "common.h"
+
+namespace goac {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ FP64 NT GEMM
+// Tile 64 x 64 x 16, 256 threads = 4 waves in a 2 x 2 grid, each wave a 32 x 32
+// block of four 16 x 16 MFMA accumulators. Operands are staged k-major in LDS so
+// every lane's MFMA operand is one 8-byte LDS read. Rows beyond M (or *M_dev) and
+// columns beyond N are skipped; K is zero-padded.
+constexpr int DG_BM = 64, DG_BN = 64, DG_BK = 16;
+
+__global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                                  int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                  double* __restrict__ C, int64_t ldc, double alpha, double beta,
+                                                  const int32_t* __restrict__ M_dev) {
+    __shared__ double As[DG_BK][DG_BM + 2];
+    __shared__ double Bs[DG_BK][DG_BN + 2];
+    if (M_dev) M = *M_dev;
+    const int64_t m0 = (int64_t)blockIdx.y * DG_BM;
+    const int64_t n0 = (int64_t)blockIdx.x * DG_BN;
+    if (m0 >= M) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    f64x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // loader mapping: each thread moves 4 consecutive k of one row
+    const int lr = tid >> 2;          // 0..63
+    const int lk = (tid & 3) * 4;     // 0, 4, 8, 12
+    for (int64_t k0 = 0; k0 < K; k0 += DG_BK) {
+        {
+            const int64_t gm = m0 + lr;
+            const int64_t gn = n0 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gk = k0 + lk + q;
+                As[lk + q][lr] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
+                Bs[lk + q][lr] = (gn < N && gk < K) ? B[gn * ldb + gk] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < DG_BK; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            const double a0 = As[kk][wm * 32 + (lane & 15)];
+            const double a1 = As[kk][wm * 32 + 16 + (lane & 15)];
+            const double b0 = Bs[kk][wn * 32 + (lane & 15)];
+            const double b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // FP64 16x16 accumulators interleave rows: D[row = lane / 16 + 4 v][col = lane % 16]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gm = m0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+                const int64_t gn = n0 + wn * 32 + b * 16 + (lane & 15);
+                if (gm < M && gn < N) {
+                    double* c = C + gm * ldc + gn;
+                    const double val = alpha * acc[a][b][v];
+                    *c = (beta == 0.0) ? val : val + beta * *c;
+                }
+            }
+}
+
+goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                     const int32_t* M_dev) {
+    if (M <= 0 || N <= 0) return GOAC_OK;
+    dim3 grid((unsigned)((N + DG_BN - 1) / DG_BN), (unsigned)((M + DG_BM - 1) / DG_BM));
+    hipLaunchKernelGGL(k_dgemm_nt, grid, dim3(256), 0, ctx->stream, M, N, K, A, lda, B, ldb, C, ldc,
+                       alpha, beta, M_dev);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
+}
+
+// ------------------------------------------------------------------ bf16 hi+lo population GEMM
+// Phi[p][n] = sum_k dQ[p][k] (Vhi[n][k] + Vlo[n][k])  (V symmetric, so rows of V
+// serve as columns), FP32 accumulation. Epilogue per output tile:
+//   part[p][tile_n] = sum_{n in tile} dQ[p][n] (ht[n] + Phi[p][n] / 2)   (FP64)
+// Tile 64 (p) x 64 (n) x 64 (k), 256 threads = 2 x 2 waves, each wave one 32 x 32
+// accumulator fed by both the hi and the lo operand.
+constexpr int PB_BM = 64, PB_BN = 64, PB_BK = 64, PB_LD = PB_BK + 8;
+
+__global__ __launch_bounds__(256) void k_pop_bf16(int64_t P, int32_t Mp, const __hip_bfloat16* __restrict__ dQ,
+                                                  const __hip_bfloat16* __restrict__ Vhi,
+                                                  const __hip_bfloat16* __restrict__ Vlo,
+                                                  const double* __restrict__ ht, double* __restrict__ part,
+                                                  int32_t n_tiles) {
+    __shared__ __align__(16) __hip_bfloat16 As[PB_BM][PB_LD];
+    __shared__ __align__(16) __hip_bfloat16 Hs[PB_BN][PB_LD];
+    __shared__ __align__(16) __hip_bfloat16 Ls[PB_BN][PB_LD];
+    __shared__ double red[PB_BM][PB_BN / 32 * 1 + 1];
+    const int64_t m0 = (int64_t)blockIdx.y * PB_BM;
+    const int n0 = blockIdx.x * PB_BN;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x16 acc = {};
+    // loader: 64 rows x 64 k bf16 = 512 chunks of 16 bytes; two per thread per matrix
+    for (int k0 = 0; k0 < Mp; k0 += PB_BK) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + q * 256;
+            const int r = idx >> 3;
+            const int c = (idx & 7) * 8;
+            const int64_t gp = m0 + r;
+            uint4 va = make_uint4(0, 0, 0, 0);
+            if (gp < P) va = *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c);
+            *reinterpret_cast<uint4*>(&As[r][c]) = va;
+            const int64_t gn = n0 + r;
+            *reinterpret_cast<uint4*>(&Hs[r][c]) = *reinterpret_cast<const uint4*>(Vhi + gn * Mp + k0 + c);
+            *reinterpret_cast<uint4*>(&Ls[r][c]) = *reinterpret_cast<const uint4*>(Vlo + gn * Mp + k0 + c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < PB_BK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Hs[wn * 32 + (lane & 31)][kk]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ls[wn * 32 + (lane & 31)][kk]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds D[i][j], j = lane % 32, i = 8 (v / 4) + 4 (lane / 32) + v % 4
+    const int j = lane & 31;
+    const int gn = n0 + wn * 32 + j;
+    const double htn = ht[gn];
+    double rows[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t gp = m0 + wm * 32 + i;
+        const double dqv = gp < P ? (double)__bfloat162float(dQ[gp * Mp + gn]) : 0.0;
+        rows[v] = dqv * (htn + 0.5 * (double)acc[v]);
+    }
+    // sum over the 32 columns of the wave (lanes with equal lane / 32), fixed order
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        double x = rows[v];
+#pragma unroll
+        for (int s = 1; s < 32; s <<= 1) x += __shfl_xor(x, s, 64);
+        rows[v] = x;
+    }
+    if (j == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            red[wm * 32 + i][wn] = rows[v];
+        }
+    }
+    __syncthreads();
+    if (tid < PB_BM) {
+        const int64_t gp = m0 + tid;
+        if (gp < P) part[gp * n_tiles + blockIdx.x] = red[tid][0] + red[tid][1];
+    }
+}
+
+// E[p] = E~ + sum over column tiles of part[p][t], in tile order
+__global__ void k_pop_finalize(int64_t P, int32_t n_tiles, const double* __restrict__ part, double E_t,
+                               double* __restrict__ E) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double s = 0.0;
+    for (int t = 0; t < n_tiles; ++t) s += part[p * n_tiles + t];
+    E[p] = E_t + s;
+}
+
+// dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M
+__global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
+                           const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
+                           const double* __restrict__ dq, __hip_bfloat16* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P * (int64_t)Mp) return;
+    const int64_t p = idx / Mp;
+    const int k = (int)(idx - p * Mp);
+    float v = 0.0f;
+    if (k < M) {
+        const int e = occ[p * n + mob[k]];
+        v = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+    }
+    out[idx] = __float2bfloat16(v);
+}
+
+// Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
+__global__ void k_build_q64(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
+                            const int32_t* __restrict__ mob, const double* __restrict__ charge,
+                            double* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P * (int64_t)Mp) return;
+    const int64_t p = idx / Mp;
+    const int k = (int)(idx - p * Mp);
+    double v = 0.0;
+    if (k < M) {
+        const int e = occ[p * n + mob[k]];
+        v = charge[e < E ? e : E - 1];
+    }
+    out[idx] = v;
+}
+
+// E[p] = E_ff + sum_k q_k (h_k + Phi_k / 2), k in order
+__global__ void k_pop_fp64_finalize(int64_t P, int32_t M, int32_t Mp, const double* __restrict__ Q,
+                                    const double* __restrict__ Phi, const double* __restrict__ h, double E_ff,
+                                    double* __restrict__ E) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double s = 0.0;
+    for (int k = 0; k < M; ++k) s += Q[p * Mp + k] * (h[k] + 0.5 * Phi[p * Mp + k]);
+    E[p] = E_ff + s;
+}
+
+goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
+                      const int32_t* mob, const double* charge, double* Q) {
+    const int64_t tot = P * (int64_t)Mp;
+    hipLaunchKernelGGL(k_build_q64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, P, n, M, Mp, E,
+                       occ, mob, charge, Q);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
+}
+
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
+    goac_ctx* ctx = pb->ctx;
+    const ProblemDev& d = pb->d;
+    const int32_t n_tiles = d.Mp / PB_BN;
+    const size_t dq_bytes = (size_t)P * d.Mp * sizeof(__hip_bfloat16);
+    const size_t part_bytes = (size_t)P * n_tiles * sizeof(double);
+    void* ws = nullptr;
+    goac_status st = workspace(ctx, round_up(dq_bytes, 256) + part_bytes, &ws);
+    if (st != GOAC_OK) return st;
+    __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
+    double* part = (double*)((char*)ws + round_up(dq_bytes, 256));
+    const int64_t tot = P * (int64_t)d.Mp;
+    hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, P, d.n, d.M,
+                       d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
+    GOAC_CHECK_LAUNCH(ctx);
+    dim3 grid((unsigned)n_tiles, (unsigned)((P + PB_BM - 1) / PB_BM));
+    hipLaunchKernelGGL(k_pop_bf16, grid, dim3(256), 0, ctx->stream, P, d.Mp, dQ, d.Vhi, d.Vlo, d.ht, part,
+                       n_tiles);
+    GOAC_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, n_tiles,
+                       part, d.E_t, E);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
+}
+
+#define GOAC_TRY_(expr)                \
+    do {                               \
+        goac_status s_ = (expr);       \
+        if (s_ != GOAC_OK) return s_;  \
+    } while (0)
+
+goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
+    goac_ctx* ctx = pb->ctx;
+    const ProblemDev& d = pb->d;
+    const size_t qb = round_up((size_t)P * d.Mp * sizeof(double), 256);
+    void* ws = nullptr;
+    goac_status st = workspace(ctx, 2 * qb, &ws);
+    if (st != GOAC_OK) return st;
+    double* Q = (double*)ws;
+    double* Phi = (double*)((char*)ws + qb);
+    GOAC_TRY_(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q));
+    st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr);
+    if (st != GOAC_OK) return st;
+    hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, d.M,
+                       d.Mp, Q, Phi, d.h, d.E_ff, E);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
+}
+
+}  // namespace goac
