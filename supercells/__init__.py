@@ -216,20 +216,22 @@ def config3():
 
 
 def _near_cubic_reps(target_cells):
-    """Integer n1 <= n2 <= n3 with product closest to target_cells and the
-    smallest spread (near-cubic); ties broken by lexicographic order."""
+    """Integer n1 <= n2 <= n3 balancing the product against target_cells and the
+    shape: minimise |ln(n1 n2 n3 / target)| + ln(n3 / n1) / 2 (ties broken by
+    lexicographic order), so that cells stay near-cubic in the lattice basis."""
     best = None
-    hi = max(1, int(round(target_cells ** (1 / 3))) + 3)
+    hi = max(2, int(round(target_cells ** (1 / 3))) * 2 + 2)
     for n1 in range(1, hi + 1):
-        for n2 in range(n1, hi + 3):
-            n3 = max(n2, int(round(target_cells / (n1 * n2))))
-            for m3 in (n3 - 1, n3, n3 + 1):
-                if m3 < n2:
-                    continue
-                key = (abs(n1 * n2 * m3 - target_cells), m3 - n1, (n1, n2, m3))
+        for n2 in range(n1, hi + 1):
+            for n3 in range(n2, hi + 1):
+                p = n1 * n2 * n3
+                if p > 2 * target_cells + 2:
+                    break
+                cost = abs(math.log(p / target_cells)) + 0.5 * math.log(n3 / n1)
+                key = (round(cost, 12), (n1, n2, n3))
                 if best is None or key < best:
                     best = key
-    return best[2]
+    return best[1]
 
 
 def config4(n_instances=512, seed=0, nmin=64, nmax=2048):

@@ -1,0 +1,275 @@
+"""GPU parity of the swap Monte Carlo (FP64 and mixed), replica exchange and
+the GA generation against the FP64 oracle.
+
+Bar: trajectories (the per-trial hash summed over trials), final occupations and
+accept counts bit-exact; tracked energies within 1e-6 eV per site (FP64) and
+1e-4 eV per site (mixed); GA children bit-exact given identical energies."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import supercells as S
+from gpu_common import two_sublattice_cell
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_2409_08808_amd")
+TOL = {0: 1e-6, 1: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return G.Context(0)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    c = S.config1()
+    return c, O.cell_matrix(c)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    c = S.config2()
+    return c, O.cell_matrix(c)
+
+
+def _compare(cell, stats, occ_g, best_g, st, prec, V):
+    n = len(cell["pos"])
+    assert np.array_equal(stats["t"], st.field("t"))
+    assert np.array_equal(stats["hash"], st.field("hash")), "trajectory hash differs"
+    assert np.array_equal(occ_g, st.occ), "final occupations differ"
+    assert np.array_equal(stats["accepts"], st.field("accepts"))
+    assert np.array_equal(stats["updates"], st.field("updates"))
+    assert np.all(stats["status"] == 0)
+    assert np.abs(stats["E"] - st.field("E")).max() / n <= TOL[prec]
+    assert np.abs(stats["best_E"] - st.field("best_E")).max() / n <= TOL[prec]
+    # the oracle's energy of the GPU's best occupation (ties among degenerate states)
+    Eb = O.energies(V, best_g, cell["charge"])
+    assert np.abs(Eb - stats["best_E"]).max() / n <= TOL[prec]
+
+
+def _run_gpu(ctx, cell, V, occ0, prec, n_trials, kT, block_len, seed, reanchor=1024, variant=0, sweeps=1,
+             chain_base=0):
+    pb = G.Problem(ctx, torch.from_numpy(V) if isinstance(V, np.ndarray) else V, cell["sublattice"],
+                   cell["species"], cell["charge"])
+    ch = G.Chains(pb, torch.from_numpy(occ0), prec, chain_base=chain_base)
+    per = n_trials // sweeps
+    for _ in range(sweeps):
+        ch.sweep(per, kT, block_len, seed=seed, reanchor_every=reanchor, trace=True, variant=variant)
+    occ, best, stats = ch.export()
+    return occ.cpu().numpy(), best.cpu().numpy(), stats
+
+
+def _run_oracle(cell, V, occ0, n_trials, kT, block_len, seed, chain_base=0):
+    st = O.MCState(occ0)
+    O.mc_run(V, cell, st, seed=seed, n_trials=n_trials, kT=kT, block_len=block_len, chain_base=chain_base)
+    return st
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mc_config1(ctx, cfg1, prec):
+    """Config 1 as stated: 64 chains x 1e4 trials, kT = 0.05 eV, seed 0."""
+    cell, V = cfg1
+    occ0 = O.init_occupations(cell, 64, seed=0)
+    st = _run_oracle(cell, V, occ0, 10000, [0.05], 10 ** 9, 0)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 10000, [0.05], 10 ** 9, 0, reanchor=256)
+    _compare(cell, stats, occ, best, st, prec, V)
+
+
+def test_mc_config1_end_to_end(ctx, cfg1):
+    # the GPU's own pair matrix (differs from the oracle's in the last bits)
+    cell, V = cfg1
+    e = cell["ewald"]
+    Vg = ctx.build_ewald(cell["lattice"], cell["pos"], e["alpha"], e["rcut"], e["kmax"])
+    occ0 = O.init_occupations(cell, 64, seed=0)
+    st = _run_oracle(cell, V, occ0, 10000, [0.05], 10 ** 9, 0)
+    occ, best, stats = _run_gpu(ctx, cell, Vg, occ0, 1, 10000, [0.05], 10 ** 9, 0)
+    _compare(cell, stats, occ, best, st, 1, V)
+
+
+@pytest.mark.parametrize("prec,reanchor,variant", [(0, 1024, 0), (1, 1024, 0), (1, 64, 0), (0, 1024, 256),
+                                                   (1, 128, 256)])
+def test_mc_config2_annealed(ctx, cfg2, prec, reanchor, variant):
+    """Config 2 cell, annealed kT 0.5 -> 0.01 eV (geometric, 20 blocks of 1000)."""
+    cell, V = cfg2
+    kT = np.geomspace(0.5, 0.01, 20)
+    occ0 = O.init_occupations(cell, 48, seed=7)
+    st = _run_oracle(cell, V, occ0, 20000, kT, 1000, 7)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 20000, kT, 1000, 7, reanchor=reanchor, variant=variant)
+    _compare(cell, stats, occ, best, st, prec, V)
+    if prec == 1:
+        # one FP64 anchor after every reanchor field updates
+        assert np.array_equal(stats["anchors"], stats["updates"] // reanchor)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mc_resume(ctx, cfg2, prec):
+    cell, V = cfg2
+    kT = np.geomspace(0.5, 0.05, 6)
+    occ0 = O.init_occupations(cell, 16, seed=3)
+    st = _run_oracle(cell, V, occ0, 6000, kT, 1000, 3)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 6000, kT, 1000, 3, sweeps=3)
+    _compare(cell, stats, occ, best, st, prec, V)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mc_two_sublattices_interleaved(ctx, prec):
+    cell = two_sublattice_cell()
+    perm = np.random.default_rng(2).permutation(len(cell["pos"]))
+    cell = S.make_cell(cell["lattice"], cell["pos"][perm], cell["sublattice"][perm], cell["species"][perm],
+                       cell["charge"], cell["names"])
+    V = O.cell_matrix(cell)
+    occ0 = O.init_occupations(cell, 24, seed=5)
+    kT = np.geomspace(1.0, 0.05, 8)
+    st = _run_oracle(cell, V, occ0, 8000, kT, 1000, 5, chain_base=100)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 8000, kT, 1000, 5, reanchor=200, chain_base=100)
+    _compare(cell, stats, occ, best, st, prec, V)
+
+
+def test_mc_config2_full_launch_sampled(ctx, cfg2):
+    """The benchmark's launch: 4096 chains x 1e5 trials, kT 0.5 -> 0.01 eV over
+    100 blocks of 1000, mixed precision, seed 0. Six chains are replayed by the
+    oracle one by one."""
+    cell, V = cfg2
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    occ0 = pb.init_occupations(4096, seed=0)
+    ch = G.Chains(pb, occ0, G.GOAC_MIXED)
+    kT = np.geomspace(0.5, 0.01, 100)
+    ch.sweep(100000, kT, 1000, seed=0, reanchor_every=1024, trace=True)
+    occ, best, stats = ch.export()
+    occ, best = occ.cpu().numpy(), best.cpu().numpy()
+    occ0 = occ0.cpu().numpy()
+    assert np.all(stats["t"] == 100000) and np.all(stats["status"] == 0)
+    for c in (0, 1, 777, 2048, 3001, 4095):
+        st = _run_oracle(cell, V, occ0[c:c + 1], 100000, kT, 1000, 0, chain_base=c)
+        assert stats["hash"][c] == st.stats[0].hash
+        assert np.array_equal(occ[c], st.occ[0])
+        assert abs(stats["E"][c] - st.stats[0].E) / 512 <= TOL[1]
+    # every chain: tracked energy against the FP64 energy of its final occupation
+    Ef = pb.energies(torch.from_numpy(occ), G.GOAC_FP64).cpu().numpy()
+    assert np.abs(Ef - stats["E"]).max() / 512 <= TOL[1]
+
+
+def test_mc_config5_mixed_equals_fp64(ctx):
+    """Config 5 cell (N = 16384, M = 8192): the mixed chain must retrace the FP64
+    chain exactly, and the tracked energies must match a fresh FP64 evaluation."""
+    cell = S.config5()
+    Vg = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, Vg, cell["sublattice"], cell["species"], cell["charge"])
+    del Vg
+    torch.cuda.empty_cache()
+    occ0 = pb.init_occupations(64, seed=0)
+    kT = np.geomspace(0.5, 0.01, 10)
+    res = {}
+    for prec in (0, 1):
+        ch = G.Chains(pb, occ0, prec)
+        ch.sweep(3000, kT, 300, seed=0, reanchor_every=1024, trace=True)
+        res[prec] = ch.export()
+        ch.close()
+    (o0, b0, s0), (o1, b1, s1) = res[0], res[1]
+    assert np.array_equal(s0["hash"], s1["hash"]) and torch.equal(o0, o1)
+    n = 16384
+    assert np.abs(s0["E"] - s1["E"]).max() / n <= TOL[1]
+    Ef = pb.energies(o0, G.GOAC_FP64).cpu().numpy()
+    assert np.abs(Ef - s0["E"]).max() / n <= TOL[0]
+    assert np.abs(Ef - s1["E"]).max() / n <= TOL[1]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mc_batch_uneven_instances(ctx, prec):
+    """Several uneven rock-salt/spinel instances in one persistent launch; each
+    instance checked against the oracle with its own instance id."""
+    cells = S.config4(n_instances=10, seed=3, nmin=40, nmax=420)
+    Vs = [O.cell_matrix(c) for c in cells]
+    pbs = [G.Problem(ctx, torch.from_numpy(V), c["sublattice"], c["species"], c["charge"]) for c, V in zip(cells, Vs)]
+    cpi = [5 + (i % 3) for i in range(len(cells))]
+    occ0 = [O.init_occupations(c, k, seed=9, instance=i) for i, (c, k) in enumerate(zip(cells, cpi))]
+    flat = np.concatenate([o.reshape(-1) for o in occ0])
+    ch = G.Chains.batch(pbs, cpi, torch.from_numpy(flat), prec)
+    kT = np.geomspace(0.3, 0.01, 4)
+    ch.sweep(4000, kT, 1000, seed=9, reanchor_every=256, trace=True)
+    occ, best, stats = ch.export()
+    occ = occ.cpu().numpy()
+    start = 0
+    row = 0
+    for i, (c, V) in enumerate(zip(cells, Vs)):
+        n = len(c["pos"])
+        st = O.MCState(occ0[i])
+        O.mc_run(V, c, st, seed=9, n_trials=4000, kT=kT, block_len=1000, instance=i)
+        k = cpi[i]
+        got = occ[start:start + k * n].reshape(k, n)
+        assert np.array_equal(got, st.occ)
+        assert np.array_equal(stats["hash"][row:row + k], st.field("hash"))
+        assert np.abs(stats["E"][row:row + k] - st.field("E")).max() / n <= TOL[prec]
+        start += k * n
+        row += k
+
+
+def test_remc_exchange_bitexact(ctx, cfg1):
+    cell, V = cfg1
+    R = 4
+    ladder = np.array([0.05, 0.1, 0.2, 0.4])
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    occ0 = pb.init_occupations(16, seed=4)
+    ch = G.Chains(pb, occ0, G.GOAC_FP64)
+    ch.set_rows(np.tile(np.arange(R), 4))
+    slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), 4), device="cuda")
+    acc = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    ref_slot = np.tile(np.arange(R, dtype=np.int32), (4, 1))
+    for x in range(6):
+        ch.sweep(500, ladder[:, None], seed=4)
+        _, _, stats = ch.export()
+        ch.remc_exchange(R, ladder, x, 77, slot, acc)
+        for g in range(4):
+            ref_slot[g], _ = O.remc_exchange(ladder, stats["E"][g * R:(g + 1) * R], ref_slot[g], x, 77, group=g)
+        assert np.array_equal(slot.view(4, R).cpu().numpy(), ref_slot)
+    _, _, stats = ch.export()
+    rows = stats["row"].reshape(4, R)
+    for g in range(4):
+        assert np.array_equal(ref_slot[g][rows[g]], np.arange(R))
+
+
+# ------------------------------------------------------------------ GA
+
+@pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96)])
+def test_ga_generation_bitexact(ctx, which, P):
+    cell = two_sublattice_cell() if which == "two" else getattr(S, which)()
+    V = torch.zeros((len(cell["pos"]),) * 2, dtype=torch.float64)
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    pop = O.init_occupations(cell, P, seed=1)
+    rng = np.random.default_rng(P)
+    E = -1000.0 + rng.normal(0.0, 3.0, P)
+    E[5] = E[9]                                 # a tie for the elite order
+    for g, (ne, pm) in enumerate([(8, 0.2), (0, 1.0), (3, 0.0)]):
+        got = pb.ga_generation(torch.from_numpy(pop), torch.from_numpy(E), seed=31, generation=g, n_elite=ne,
+                               p_mut=pm).cpu().numpy()
+        ref = O.ga_generation(cell, pop, E, seed=31, g=g, n_elite=ne, p_mut=pm)
+        assert np.array_equal(got, ref)
+    # uniform selection when all energies are equal
+    got = pb.ga_generation(torch.from_numpy(pop), torch.zeros(P, dtype=torch.float64), seed=3, generation=9,
+                           n_elite=2, p_mut=0.5).cpu().numpy()
+    assert np.array_equal(got, O.ga_generation(cell, pop, np.zeros(P), seed=3, g=9, n_elite=2, p_mut=0.5))
+
+
+def test_ga_weight_overflow_is_an_error(ctx, cfg1):
+    cell, V = cfg1
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    pop = pb.init_occupations(8, seed=0)
+    E = torch.tensor([0.0, 1e40] + [0.0] * 6, dtype=torch.float64)
+    with pytest.raises(G.GoacError) as e:
+        pb.ga_generation(pop, E, seed=0, generation=0)
+    assert e.value.status == "EINVAL"
+
+
+def test_chains_reject_broken_composition(ctx, cfg1):
+    cell, V = cfg1
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    occ = pb.init_occupations(4, seed=0)
+    occ[2, 0] = 1 if occ[2, 0].item() == 2 else 2      # one Li <-> M change: counts break
+    with pytest.raises(G.GoacError) as e:
+        G.Chains(pb, occ, G.GOAC_FP64)
+    assert e.value.status == "EINVAL"
