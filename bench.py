@@ -1,0 +1,233 @@
+"""Benchmark of the Coulomb cluster-expansion hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input, the
+4x4x4 rock-salt supercell (N = 512; 256 O2- fixed; Li+ 128, Ni2+ 32, Co3+ 64,
+Mn4+ 32 on 256 cation positions):
+  1. FP64 Ewald pair matrix (real-space erfc + reciprocal sum on matrix cores)
+  2. problem derivation (mobile block in FP64/FP32/bf16 hi+lo, fixed-ion field)
+  3. 4096 random starts, 4096 chains
+  4. 4096 chains x 1e5 swap trials, kT 0.5 -> 0.01 eV geometric over 100 blocks
+     of 1000 trials; FP32 field with FP64 re-anchoring every 1024 field updates
+  5. energies of the 4096 best occupations (bf16 hi+lo matrix-core product)
+  6. one GA generation on them (8 elites, mutation rate 0.2)
+  7. FP64 top-64 of the 4096 best occupations
+value = swap trials per second over whole steps (inputs resident on the GPU).
+
+Also measured: the same step with the FP64 field and FP64 energies ("plain
+FP64"), and population energies per second of the GA workload (8x8x8 rock-salt,
+N = 4096, P = 1024, 200 generations: bf16 hi+lo energies, GA generation).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC swap-trials/s and config energies/s, mixed+batched vs plain FP64, 1 GPU"
+CHAINS, TRIALS, BLOCKS, BLOCK_LEN = 4096, 100000, 100, 1000
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit or FP64 VALU lane operations per second
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+BF16_PEAK = 2.5e15
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-FP64 and GA-energies legs")
+    ap.add_argument("--calibrate-copy", action="store_true", help="also run a copy kernel of known size")
+    ap.add_argument("--ga-generations", type=int, default=200)
+    return ap.parse_args()
+
+
+def algorithmic_ops(trials, updates, M):
+    """VALU lane-operations a trial and a field update need at minimum:
+    Philox4x32-10 80 (10 rounds of 2 mul-lo, 2 mul-hi, 4 xor), two index maps 4,
+    the uniform 4, dE 10, the Metropolis test 20 (one logarithm); a field update
+    2 fused multiply-adds per mobile position."""
+    return trials * 118.0 + updates * 2.0 * M
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the hot path shards chains, instances and "
+              "populations without communication, but this build measures a single "
+              "MI355X only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2409_08808_amd as G
+    import supercells as S
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = G.Context(0, stream)
+    cell = S.config2()
+    kT = np.geomspace(0.5, 0.01, BLOCKS)
+
+    def step(seed, prec, ev=None):
+        V = ctx.build_ewald(cell["lattice"], cell["pos"])
+        pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+        occ0 = pb.init_occupations(CHAINS, seed=seed)
+        ch = G.Chains(pb, occ0, prec)
+        if ev is not None:
+            ev[0].record(stream)
+        ch.sweep(TRIALS, kT, BLOCK_LEN, seed=seed, reanchor_every=1024)
+        if ev is not None:
+            ev[1].record(stream)
+        occ, best, stats = ch.export()
+        best = best.view(CHAINS, -1)
+        E = pb.energies(best, G.GOAC_MIXED if prec == G.GOAC_MIXED else G.GOAC_FP64)
+        pb.ga_generation(best, E, seed=seed, generation=0, n_elite=8, p_mut=0.2)
+        idx, Ek = pb.topk(best, 64)
+        torch.cuda.synchronize()
+        ch.close()
+        pb.close()
+        return stats
+
+    def timed(prec, steps, warmup):
+        for w in range(warmup):
+            step(1000 + w, prec)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        stats = None
+        for k in range(steps):
+            stats = step(k, prec, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern = np.array([a.elapsed_time(b) for a, b in evs]) * 1e-3
+        print("  [%s] %d steps in %.3f s; sweep %.2f ms avg" % ("mixed" if prec else "fp64", steps, wall,
+                                                               1e3 * kern.mean()), file=sys.stderr, flush=True)
+        return wall, kern, stats
+
+    wall, kern, stats = timed(G.GOAC_MIXED, args.steps, args.warmup)
+    total_trials = float(CHAINS) * TRIALS * args.steps
+    value = total_trials / wall
+    M = 256
+    upd = float(stats["updates"].sum())
+    ops = algorithmic_ops(float(CHAINS) * TRIALS, upd, M)
+    achieved = ops / kern.mean()
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "swap-trials/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "rock-salt 4x4x4 (N=512, M=256; Li/Ni/Co/Mn 128/32/64/32), 4096 chains x 1e5 "
+                               "trials, kT 0.5->0.01 eV over 100 blocks, FP32 field + FP64 re-anchor/1024, "
+                               "then bf16 energies, GA generation and FP64 top-64 of the chain bests",
+                   "chains": CHAINS, "trials_per_chain": TRIALS, "parallelism": "chains per workgroup"},
+        "mc_sweep_ms": 1e3 * kern.mean(),
+        "mc_trials_per_s_kernel": CHAINS * TRIALS / kern.mean(),
+        "accept_rate": float(stats["accepts"].sum()) / (CHAINS * TRIALS),
+        "field_updates_per_chain": upd / CHAINS,
+        "fallbacks_per_chain": float(stats["fallbacks"].sum()) / CHAINS,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                     "kernel": "k_mc<mixed>", "ops_per_launch": ops},
+    }
+    if not args.no_extras:
+        w64, k64, s64 = timed(G.GOAC_FP64, max(2, args.steps // 2), 1)
+        result["plain_fp64_trials_per_s"] = float(CHAINS) * TRIALS * max(2, args.steps // 2) / w64
+        result["plain_fp64_sweep_ms"] = 1e3 * k64.mean()
+        result["mixed_vs_fp64"] = result["value"] / result["plain_fp64_trials_per_s"]
+        result.update(ga_energies(ctx, G, S, torch, stream, args.ga_generations))
+    if args.calibrate_copy:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = 2 * x.numel()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(S)
+    print(json.dumps(result), flush=True)
+
+
+def ga_energies(ctx, G, S, torch, stream, generations):
+    """GA workload: 8x8x8 rock-salt (N = 4096), P = 1024, `generations`
+    generations; energies/s counts only the population-energy calls."""
+    cell = S.config3()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    del V
+    out = {}
+    for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+        pop = pb.init_occupations(1024, seed=0)
+        E = torch.empty(1024, dtype=torch.float64, device=pop.device)
+        pb.energies(pop, prec, out=E)                      # warm-up
+        torch.cuda.synchronize()
+        t_en = 0.0
+        t0 = time.perf_counter()
+        gens = generations if prec == G.GOAC_MIXED else max(10, generations // 10)
+        for g in range(gens):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            pb.energies(pop, prec, out=E)
+            b.record(stream)
+            pop = pb.ga_generation(pop, E, seed=0, generation=g, n_elite=8, p_mut=0.2)
+            b.synchronize()
+            t_en += a.elapsed_time(b) * 1e-3
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["ga_%s_energies_per_s" % name] = 1024 * gens / t_en
+        out["ga_%s_energy_call_us" % name] = 1e6 * t_en / gens
+        out["ga_%s_generation_ms" % name] = 1e3 * wall / gens
+        if prec == G.GOAC_MIXED:
+            flops = 2 * 2.0 * 1024 * 2048 * 2048
+            out["ga_mixed_mfma_frac"] = flops / (t_en / gens) / BF16_PEAK
+    out["energies_per_s"] = out["ga_mixed_energies_per_s"]
+    pb.close()
+    return out
+
+
+def cpu_baseline(S):
+    """The FP64 oracle (unchanged) on the host cores: one full step of the same
+    workload (Ewald matrix, 4096 chains x 1e5 trials, energies of the bests, a
+    GA generation, top-64), OpenMP over rows, chains and configurations."""
+    import oracle as O
+    cell = S.config2()
+    nthreads = O.num_threads()
+    t0 = time.perf_counter()
+    V = O.cell_matrix(cell)
+    occ0 = O.init_occupations(cell, CHAINS, seed=0)
+    st = O.MCState(occ0)
+    O.mc_run(V, cell, st, seed=0, n_trials=TRIALS, kT=np.geomspace(0.5, 0.01, BLOCKS), block_len=BLOCK_LEN)
+    E = O.energies(V, st.best_occ, cell["charge"])
+    O.ga_generation(cell, st.best_occ, E, seed=0, g=0, n_elite=8, p_mut=0.2)
+    O.topk(V, st.best_occ, cell["charge"], 64)
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": CHAINS * TRIALS / dt, "unit": "swap-trials/s", "cores": nthreads, "kind": "oracle",
+            "sample": "one full step of the workload (4096 chains x 1e5 trials plus Ewald, energies, GA, "
+                      "top-64) in %.1f s" % dt, "cpu": model}
+
+
+if __name__ == "__main__":
+    main()

@@ -15,26 +15,28 @@ goac_status energies_fp64(goac_problem*, int64_t, const uint8_t*, double*);
 
 __global__ void k_init(int64_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
                        int32_t, const uint8_t*, uint64_t, uint32_t, uint32_t, uint8_t*);
-__global__ void k_ga_prep(int64_t, const double*, int32_t, uint64_t*, int32_t*, int32_t*);
+__global__ void k_ga_prep(int64_t, const double*, uint64_t*, int32_t*);
 __global__ void k_ga_child(int64_t, int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*,
                            const uint8_t*, const int32_t*, const int32_t*, int32_t, const uint8_t*, int64_t,
                            const uint8_t*, const uint64_t*, const int32_t*, int32_t, uint64_t, uint32_t, double,
                            uint8_t*);
-__global__ void k_topk_select(int64_t, int32_t, const double*, int64_t*, double*);
+goac_status rank_select(goac_ctx*, int64_t, const double*, int32_t, int32_t*, int64_t*, int32_t*, double*);
 
-goac_status workspace(goac_ctx* ctx, size_t bytes, void** out) {
-    if (bytes > ctx->ws_size) {
-        if (ctx->ws) {
+goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
+    if (slot < 0 || slot >= kWsSlots) return fail(ctx, GOAC_EINVAL, "workspace slot");
+    if (bytes > ctx->ws_size[slot]) {
+        if (ctx->ws[slot]) {
+            // work already queued may still read the old buffer
             GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            GOAC_HIP(ctx, hipFree(ctx->ws));
-            ctx->ws = nullptr;
-            ctx->ws_size = 0;
+            GOAC_HIP(ctx, hipFree(ctx->ws[slot]));
+            ctx->ws[slot] = nullptr;
+            ctx->ws_size[slot] = 0;
         }
         const size_t sz = round_up((int64_t)bytes, 1 << 20);
-        GOAC_HIP(ctx, hipMalloc(&ctx->ws, sz));
-        ctx->ws_size = sz;
+        GOAC_HIP(ctx, hipMalloc(&ctx->ws[slot], sz));
+        ctx->ws_size[slot] = sz;
     }
-    *out = ctx->ws;
+    *out = ctx->ws[slot];
     return GOAC_OK;
 }
 
@@ -59,78 +61,127 @@ __global__ void k_extract(int64_t n, int32_t M, int32_t Mp, const double* __rest
     Vlo[idx] = __float2bfloat16((float)rest);
 }
 
-// per mobile row k: diag, rowmax (rounded up), h_k = sum_f V[f][mob_k] q_f over
-// the fixed sites (V symmetric), vc_k = sum_l V64[l][k] c_l and the field of the
-// reference occupation phi_k = h_k + sum_l V64[l][k] q_l
-__global__ void k_rows(int64_t n, int32_t M, int32_t Mp, const double* __restrict__ V, const int32_t* __restrict__ mob,
-                       const int32_t* __restrict__ fixed_idx, const double* __restrict__ fixed_q, int32_t n_fixed,
-                       const double* __restrict__ V64, const double* __restrict__ cvec, const double* __restrict__ qref,
-                       double* __restrict__ diag, float* __restrict__ rowmax, double* __restrict__ rowabs,
-                       double* __restrict__ h, double* __restrict__ vc, double* __restrict__ phiref) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline double wsum64(double x) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline double wmax64(double x) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// one wavefront per mobile row k: diag, rowmax (rounded up), rowabs = sum_l |V_kl|,
+// h_k = sum_f V[mob_k][f] q_f over the fixed sites, vc_k = sum_l V_kl c_l and the
+// field of the reference occupation phiref_k = h_k + sum_l V_kl q_l (fixed-order
+// butterfly sums)
+__global__ __launch_bounds__(256) void k_rows(int64_t n, int32_t M, int32_t Mp, const double* __restrict__ V,
+                                              const int32_t* __restrict__ mob, const int32_t* __restrict__ fixed_idx,
+                                              const double* __restrict__ fixed_q, int32_t n_fixed,
+                                              const double* __restrict__ V64, const double* __restrict__ cvec,
+                                              const double* __restrict__ qref, double* __restrict__ diag,
+                                              float* __restrict__ rowmax, double* __restrict__ rowabs,
+                                              double* __restrict__ h, double* __restrict__ vc,
+                                              double* __restrict__ phiref) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (k >= Mp) return;
     if (k >= M) {
-        h[k] = 0.0;
-        vc[k] = 0.0;
+        if (lane == 0) {
+            h[k] = 0.0;
+            vc[k] = 0.0;
+        }
         return;
     }
-    const int64_t mk = mob[k];
+    const double* row = V + (int64_t)mob[k] * n;
     double hs = 0.0;
-    for (int f = 0; f < n_fixed; ++f) hs += V[(int64_t)fixed_idx[f] * n + mk] * fixed_q[f];
+    for (int f = lane; f < n_fixed; f += 64) hs += row[fixed_idx[f]] * fixed_q[f];
+    const double* r64 = V64 + (int64_t)k * Mp;
     double s1 = 0.0, s2 = 0.0, mx = 0.0, ab = 0.0;
-    for (int l = 0; l < M; ++l) {
-        const double v = V64[(int64_t)l * Mp + k];
+    for (int l = lane; l < M; l += 64) {
+        const double v = r64[l];
         s1 += v * cvec[l];
         s2 += v * qref[l];
         mx = fmax(mx, fabs(v));
         ab += fabs(v);
     }
-    rowabs[k] = ab;
-    diag[k] = V64[(int64_t)k * Mp + k];
-    float r = (float)mx;
-    if ((double)r < mx) r = nextafterf(r, INFINITY);
-    rowmax[k] = r;
-    h[k] = hs;
-    vc[k] = s1;
-    phiref[k] = hs + s2;
+    hs = wsum64(hs);
+    s1 = wsum64(s1);
+    s2 = wsum64(s2);
+    mx = wmax64(mx);
+    ab = wsum64(ab);
+    if (lane == 0) {
+        diag[k] = r64[k];
+        float r = (float)mx;
+        if ((double)r < mx) r = nextafterf(r, INFINITY);
+        rowmax[k] = r;
+        rowabs[k] = ab;
+        h[k] = hs;
+        vc[k] = s1;
+        phiref[k] = hs + s2;
+    }
 }
 
-// fixed-ion energy terms: out[f] = q_f sum_f' V[f][f'] q_f'
-__global__ void k_fixed_energy(int64_t n, const int32_t* __restrict__ fixed_idx, const double* __restrict__ fixed_q,
-                               int32_t n_fixed, const double* __restrict__ V, double* __restrict__ out) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// fixed-ion energy terms, one wavefront per fixed row: out[f] = q_f sum_g V[f][g] q_g
+__global__ __launch_bounds__(256) void k_fixed_energy(int64_t n, const int32_t* __restrict__ fixed_idx,
+                                                      const double* __restrict__ fixed_q, int32_t n_fixed,
+                                                      const double* __restrict__ V, double* __restrict__ out) {
+    const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (f >= n_fixed) return;
-    const int64_t a = fixed_idx[f];
+    const double* row = V + (int64_t)fixed_idx[f] * n;
     double s = 0.0;
-    for (int g = 0; g < n_fixed; ++g) s += V[(int64_t)fixed_idx[g] * n + a] * fixed_q[g];
-    out[f] = fixed_q[f] * s;
+    for (int g = lane; g < n_fixed; g += 64) s += row[fixed_idx[g]] * fixed_q[g];
+    s = wsum64(s);
+    if (lane == 0) out[f] = fixed_q[f] * s;
 }
 
-// single-thread sums in index order (deterministic):
+// one workgroup, fixed-order sums (per-thread strided partials, then a tree):
 //   out[0] = E_ff = 1/2 sum efix,  out[1] = E~ = E_ff + sum c_k h_k + 1/2 sum c_k vc_k,
-//   out[2 + s] = mean of phiref over sublattice s; ht_k = h_k + vc_k
-__global__ void k_derive_scalars(int32_t M, int32_t n_fixed, int32_t S, const double* __restrict__ efix,
-                                 const double* __restrict__ cvec, const double* __restrict__ h,
-                                 const double* __restrict__ vc, const double* __restrict__ phiref,
-                                 const uint8_t* __restrict__ msub, double* __restrict__ ht,
-                                 double* __restrict__ phibar, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double e = 0.0;
-    for (int f = 0; f < n_fixed; ++f) e += efix[f];
-    const double Eff = 0.5 * e;
-    double ch = 0.0, cvc = 0.0;
-    for (int k = 0; k < M; ++k) {
+//   phibar[s] = mean of phiref over sublattice s; ht_k = h_k + vc_k
+__global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fixed, int32_t S,
+                                                        const double* __restrict__ efix,
+                                                        const double* __restrict__ cvec,
+                                                        const double* __restrict__ h,
+                                                        const double* __restrict__ vc,
+                                                        const double* __restrict__ phiref,
+                                                        const uint8_t* __restrict__ msub, double* __restrict__ ht,
+                                                        double* __restrict__ phibar, double* __restrict__ out) {
+    __shared__ double red[3 + kMaxSub][256];
+    __shared__ int cnt[kMaxSub][256];
+    const int t = threadIdx.x;
+    double e = 0.0, ch = 0.0, cvc = 0.0;
+    double acc[kMaxSub];
+    int nc[kMaxSub];
+    for (int s = 0; s < kMaxSub; ++s) { acc[s] = 0.0; nc[s] = 0; }
+    for (int f = t; f < n_fixed; f += 256) e += efix[f];
+    for (int k = t; k < M; k += 256) {
         ch += cvec[k] * h[k];
         cvc += cvec[k] * vc[k];
         ht[k] = h[k] + vc[k];
+        const int s = msub[k];
+        for (int q = 0; q < kMaxSub; ++q)
+            if (q == s) { acc[q] += phiref[k]; nc[q] += 1; }
     }
-    out[0] = Eff;
-    out[1] = Eff + ch + 0.5 * cvc;
-    double acc[kMaxSub];
-    int cnt[kMaxSub];
-    for (int s = 0; s < S; ++s) { acc[s] = 0.0; cnt[s] = 0; }
-    for (int k = 0; k < M; ++k) { acc[msub[k]] += phiref[k]; cnt[msub[k]] += 1; }
-    for (int s = 0; s < S; ++s) phibar[s] = cnt[s] ? acc[s] / cnt[s] : 0.0;
+    red[0][t] = e;
+    red[1][t] = ch;
+    red[2][t] = cvc;
+    for (int s = 0; s < kMaxSub; ++s) { red[3 + s][t] = acc[s]; cnt[s][t] = nc[s]; }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int r = 0; r < 3 + kMaxSub; ++r) red[r][t] += red[r][t + w];
+            for (int s = 0; s < kMaxSub; ++s) cnt[s][t] += cnt[s][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double Eff = 0.5 * red[0][0];
+        out[0] = Eff;
+        out[1] = Eff + red[1][0] + 0.5 * red[2][0];
+        for (int s = 0; s < S; ++s) phibar[s] = cnt[s][0] ? red[3 + s][0] / cnt[s][0] : 0.0;
+    }
 }
 
 // ------------------------------------------------------------------ chain kernels
@@ -157,34 +208,51 @@ __global__ void k_check_comp(int64_t n, int32_t M, int32_t S, int32_t E, const i
 }
 
 // mobile occupation, perm (positions of each sublattice sorted by (species,
-// position)) and the best copy of one chain
-__global__ void k_chain_setup(int64_t n, int32_t M, int32_t Mp, int32_t S, int32_t E, const int32_t* __restrict__ tab,
-                              const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
-                              const uint8_t* __restrict__ occ, int64_t first, const int64_t* __restrict__ offs,
-                              uint8_t* __restrict__ occ_m, uint16_t* __restrict__ perm, uint8_t* __restrict__ best) {
+// position)) and the best copy of one chain; one wavefront per chain. Within a
+// 64-position chunk the rank of a position among equal (sublattice, species)
+// keys is a popcount of a ballot; running counts carry across chunks.
+__global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_t Mp, int32_t S, int32_t E,
+                                                    const int32_t* __restrict__ tab, const int32_t* __restrict__ mob,
+                                                    const uint8_t* __restrict__ msub, const uint8_t* __restrict__ occ,
+                                                    int64_t first, const int64_t* __restrict__ offs,
+                                                    uint8_t* __restrict__ occ_m, uint16_t* __restrict__ perm,
+                                                    uint8_t* __restrict__ best) {
     __shared__ int next[kMaxSub * kMaxSpecies];
     const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
     const int64_t off = offs[first + c];
     const uint8_t* row = occ + c * n;
-    for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
-        const uint8_t e = k < M ? row[mob[k]] : 0;
-        occ_m[off + k] = e;
-        best[off + k] = e;
-        if (k >= M) perm[off + k] = 0;
-    }
     const int32_t* subsize = tab + 2;
     const int32_t* suboff = subsize + S;
     const int32_t* offs_se = suboff + S + S * E;
-    for (int x = threadIdx.x; x < S * E; x += blockDim.x) next[x] = suboff[x / E] + offs_se[x];
+    for (int x = lane; x < S * E; x += 64) next[x] = suboff[x / E] + offs_se[x];
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int k = 0; k < M; ++k) {
-            const int e = row[mob[k]];
-            const int s = msub[k];
-            if (e >= E) continue;                      // rejected by the composition check
-            const int at = next[s * E + e]++;
-            if (at < suboff[s] + subsize[s]) perm[off + at] = (uint16_t)k;
+    for (int k0 = 0; k0 < Mp; k0 += 64) {
+        const int k = k0 + lane;
+        const bool mobile = k < M;
+        const int e = mobile ? row[mob[k]] : 0;
+        const int s = mobile ? msub[k] : 0;
+        const int key = (mobile && e < E) ? s * E + e : -1;
+        occ_m[off + k] = (uint8_t)e;
+        best[off + k] = (uint8_t)e;
+        if (!mobile) perm[off + k] = 0;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        // each distinct key of the chunk in turn (uniform loop)
+        uint64_t todo = __ballot(key >= 0);
+        while (todo) {
+            const int leader = (int)__ffsll((long long)todo) - 1;
+            const int kk = __shfl(key, leader, 64);
+            const uint64_t m = __ballot(key == kk);
+            if (key == kk) {
+                const int at = next[kk] + __popcll(m & below);
+                if (at < suboff[s] + subsize[s]) perm[off + at] = (uint16_t)k;
+            }
+            __syncthreads();
+            if (lane == 0) next[kk] += __popcll(m);
+            __syncthreads();
+            todo &= ~m;
         }
+    }
 }
 
 // field and energy of every chain of one instance from Phi = Q V_mm (FP64):
@@ -340,12 +408,19 @@ goac_status dalloc(goac_ctx* ctx, T** p, size_t count, DevAllocs* track = nullpt
         if (s_ != GOAC_OK) return s_;         \
     } while (0)
 
+// Byte offsets of the sub-arrays of one device arena (256-byte aligned).
+struct ArenaPlan {
+    size_t end = 0;
+    size_t take(size_t bytes) {
+        const size_t o = (size_t)round_up((int64_t)end, 256);
+        end = o + std::max<size_t>(bytes, 1);
+        return o;
+    }
+};
+
 void problem_free(goac_problem* pb) {
-    ProblemDev& d = pb->d;
-    void* ptrs[] = {d.mob, d.msub, d.ref_occ, d.V64, d.V32, d.Vhi, d.Vlo, d.diag, d.rowmax, d.rowabs, d.h, d.ht, d.phibar,
-                    d.charge, d.dq, d.tab, pb->spos, pb->spos_inv, pb->fixed_idx};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    if (pb->arena) (void)hipFree(pb->arena);
+    pb->arena = nullptr;
 }
 
 }  // namespace
@@ -368,10 +443,9 @@ extern "C" goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** 
 
 extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->ws) {
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(ctx->ws);
-    }
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int q = 0; q < kWsSlots; ++q)
+        if (ctx->ws[q]) (void)hipFree(ctx->ws[q]);
     delete ctx;
 }
 
@@ -494,76 +568,84 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     pb->charge_host.assign(charge, charge + E);
     pb->shift_host = shift;
     pb->n_fixed = (int32_t)fixed.size();
-    goac_status st = GOAC_OK;
     auto bail = [&](goac_status s) {
         problem_free(pb);
         delete pb;
         return s;
     };
-#define PB_ALLOC(ptr, count)                                   \
-    if ((st = dalloc(ctx, &(ptr), (count))) != GOAC_OK) return bail(st);
-    PB_ALLOC(d.mob, M);
-    PB_ALLOC(d.msub, Mp);
-    PB_ALLOC(d.ref_occ, n);
-    PB_ALLOC(d.V64, (size_t)M * Mp);
-    PB_ALLOC(d.V32, (size_t)M * Mp);
-    PB_ALLOC(d.Vhi, (size_t)Mp * Mp);
-    PB_ALLOC(d.Vlo, (size_t)Mp * Mp);
-    PB_ALLOC(d.diag, M);
-    PB_ALLOC(d.rowmax, M);
-    PB_ALLOC(d.rowabs, M);
-    PB_ALLOC(d.h, Mp);
-    PB_ALLOC(d.ht, Mp);
-    PB_ALLOC(d.phibar, kMaxSub);
-    PB_ALLOC(d.charge, E);
-    PB_ALLOC(d.dq, S * E);
-    PB_ALLOC(d.tab, tab.size());
-    PB_ALLOC(pb->spos, M);
-    PB_ALLOC(pb->spos_inv, M);
-    PB_ALLOC(pb->fixed_idx, fixed.size() + 1);
-#undef PB_ALLOC
-    hipStream_t sm = ctx->stream;
-#define PB_COPY(dst, src, bytes)                                                                     \
-    if (hipMemcpyAsync((dst), (src), (bytes), hipMemcpyHostToDevice, sm) != hipSuccess) {            \
-        ctx->err = "problem_create: upload failed";                                                 \
-        return bail(GOAC_EHIP);                                                                     \
-    }
-    PB_COPY(d.mob, mob.data(), M * 4);
-    PB_COPY(d.msub, msub.data(), Mp);
-    PB_COPY(d.ref_occ, species, n);
-    PB_COPY(d.charge, charge, E * 8);
-    PB_COPY(d.dq, dq.data(), S * E * 8);
-    PB_COPY(d.tab, tab.data(), tab.size() * 4);
-    PB_COPY(pb->spos, spos.data(), M * 4);
-    PB_COPY(pb->spos_inv, spos_inv.data(), M * 4);
-    if (!fixed.empty()) PB_COPY(pb->fixed_idx, fixed.data(), fixed.size() * 4);
-    // scratch for the derivation: fixed q, cvec, qref, efix, vc, phiref, scalars
+    // one arena: the uploaded tables (one copy from a packed host image), then the
+    // derived device-only arrays
     const int32_t nf = (int32_t)fixed.size();
-    const size_t b_fq = round_up((nf + 1) * 8, 256), b_m = round_up(Mp * 8, 256);
-    void* ws = nullptr;
-    if ((st = workspace(ctx, b_fq * 2 + b_m * 4 + 256, &ws)) != GOAC_OK) return bail(st);
-    char* p = (char*)ws;
-    double* w_fq = (double*)p; p += b_fq;
-    double* w_efix = (double*)p; p += b_fq;
-    double* w_c = (double*)p; p += b_m;
-    double* w_q = (double*)p; p += b_m;
-    double* w_vc = (double*)p; p += b_m;
-    double* w_phi = (double*)p; p += b_m;
-    double* w_out = (double*)p;
-    if (nf) PB_COPY(w_fq, fq.data(), nf * 8);
-    PB_COPY(w_c, cvec.data(), Mp * 8);
-    PB_COPY(w_q, qref.data(), Mp * 8);
-#undef PB_COPY
+    ArenaPlan ap;
+    const size_t o_mob = ap.take(M * 4), o_msub = ap.take(Mp), o_ref = ap.take(n), o_chg = ap.take(E * 8),
+                 o_dq = ap.take(S * E * 8), o_tab = ap.take(tab.size() * 4), o_spos = ap.take(M * 4),
+                 o_sinv = ap.take(M * 4), o_fix = ap.take((nf + 1) * 4), o_fq = ap.take((nf + 1) * 8),
+                 o_c = ap.take(Mp * 8), o_q = ap.take(Mp * 8);
+    const size_t up_end = ap.end;
+    const size_t o_V64 = ap.take((size_t)M * Mp * 8), o_V32 = ap.take((size_t)M * Mp * 4),
+                 o_hi = ap.take((size_t)Mp * Mp * 2), o_lo = ap.take((size_t)Mp * Mp * 2), o_diag = ap.take(M * 8),
+                 o_rmax = ap.take(M * 4), o_rabs = ap.take(M * 8), o_h = ap.take(Mp * 8), o_ht = ap.take(Mp * 8),
+                 o_pbar = ap.take(kMaxSub * 8), o_efix = ap.take((nf + 1) * 8), o_vc = ap.take(Mp * 8),
+                 o_phi = ap.take(Mp * 8), o_out = ap.take(64);
+    if (hipMalloc(&pb->arena, ap.end) != hipSuccess) {
+        ctx->err = "problem_create: device allocation failed";
+        return bail(GOAC_ENOMEM);
+    }
+    char* base = (char*)pb->arena;
+    d.mob = (int32_t*)(base + o_mob);
+    d.msub = (uint8_t*)(base + o_msub);
+    d.ref_occ = (uint8_t*)(base + o_ref);
+    d.charge = (double*)(base + o_chg);
+    d.dq = (double*)(base + o_dq);
+    d.tab = (int32_t*)(base + o_tab);
+    pb->spos = (int32_t*)(base + o_spos);
+    pb->spos_inv = (int32_t*)(base + o_sinv);
+    pb->fixed_idx = (int32_t*)(base + o_fix);
+    double* w_fq = (double*)(base + o_fq);
+    double* w_c = (double*)(base + o_c);
+    double* w_q = (double*)(base + o_q);
+    d.V64 = (double*)(base + o_V64);
+    d.V32 = (float*)(base + o_V32);
+    d.Vhi = (__hip_bfloat16*)(base + o_hi);
+    d.Vlo = (__hip_bfloat16*)(base + o_lo);
+    d.diag = (double*)(base + o_diag);
+    d.rowmax = (float*)(base + o_rmax);
+    d.rowabs = (double*)(base + o_rabs);
+    d.h = (double*)(base + o_h);
+    d.ht = (double*)(base + o_ht);
+    d.phibar = (double*)(base + o_pbar);
+    double* w_efix = (double*)(base + o_efix);
+    double* w_vc = (double*)(base + o_vc);
+    double* w_phi = (double*)(base + o_phi);
+    double* w_out = (double*)(base + o_out);
+    std::vector<char> img(up_end, 0);
+    std::memcpy(img.data() + o_mob, mob.data(), M * 4);
+    std::memcpy(img.data() + o_msub, msub.data(), Mp);
+    std::memcpy(img.data() + o_ref, species, n);
+    std::memcpy(img.data() + o_chg, charge, E * 8);
+    std::memcpy(img.data() + o_dq, dq.data(), S * E * 8);
+    std::memcpy(img.data() + o_tab, tab.data(), tab.size() * 4);
+    std::memcpy(img.data() + o_spos, spos.data(), M * 4);
+    std::memcpy(img.data() + o_sinv, spos_inv.data(), M * 4);
+    if (nf) std::memcpy(img.data() + o_fix, fixed.data(), nf * 4);
+    if (nf) std::memcpy(img.data() + o_fq, fq.data(), nf * 8);
+    std::memcpy(img.data() + o_c, cvec.data(), Mp * 8);
+    std::memcpy(img.data() + o_q, qref.data(), Mp * 8);
+    hipStream_t sm = ctx->stream;
+    if (hipMemcpyAsync(base, img.data(), up_end, hipMemcpyHostToDevice, sm) != hipSuccess) {
+        ctx->err = "problem_create: upload failed";
+        return bail(GOAC_EHIP);
+    }
     {
         const int64_t tot = (int64_t)Mp * Mp;
         hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, sm, n, M, Mp, V, d.mob, d.V64,
                            d.V32, d.Vhi, d.Vlo);
-        hipLaunchKernelGGL(k_rows, dim3((unsigned)((Mp + 127) / 128)), dim3(128), 0, sm, n, M, Mp, V, d.mob,
+        hipLaunchKernelGGL(k_rows, dim3((unsigned)((Mp + 3) / 4)), dim3(256), 0, sm, n, M, Mp, V, d.mob,
                            pb->fixed_idx, w_fq, nf, d.V64, w_c, w_q, d.diag, d.rowmax, d.rowabs, d.h, w_vc, w_phi);
         if (nf)
-            hipLaunchKernelGGL(k_fixed_energy, dim3((unsigned)((nf + 127) / 128)), dim3(128), 0, sm, n, pb->fixed_idx,
+            hipLaunchKernelGGL(k_fixed_energy, dim3((unsigned)((nf + 3) / 4)), dim3(256), 0, sm, n, pb->fixed_idx,
                                w_fq, nf, V, w_efix);
-        hipLaunchKernelGGL(k_derive_scalars, dim3(1), dim3(1), 0, sm, M, nf, S, w_efix, w_c, d.h, w_vc, w_phi,
+        hipLaunchKernelGGL(k_derive_scalars, dim3(1), dim3(256), 0, sm, M, nf, S, w_efix, w_c, d.h, w_vc, w_phi,
                            d.msub, d.ht, d.phibar, w_out);
         if (hipGetLastError() != hipSuccess) {
             ctx->err = "problem_create: launch failed";
@@ -646,16 +728,13 @@ extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || k <= 0 || k > P || !occ || !idx || !Eout) return fail(ctx, GOAC_EINVAL, "topk: bad arguments");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    double* E = nullptr;
-    GOAC_HIP(ctx, hipMallocAsync((void**)&E, P * 8, ctx->stream));
-    goac_status st = energies_fp64(pb, P, occ, E);
-    if (st == GOAC_OK) {
-        hipLaunchKernelGGL(k_topk_select, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, k, E, idx,
-                           Eout);
-        if (hipGetLastError() != hipSuccess) st = fail(ctx, GOAC_EHIP, "topk: launch failed");
-    }
-    (void)hipFreeAsync(E, ctx->stream);
-    return st;
+    const size_t bE = round_up(P * 8, 256), bC = round_up(((P + 1023) / 1024) * P * 4, 256);
+    void* sel = nullptr;
+    GOAC_TRY(workspace(ctx, 2, bE + bC, &sel));
+    double* E = (double*)sel;
+    int32_t* cnt = (int32_t*)((char*)sel + bE);
+    GOAC_TRY(energies_fp64(pb, P, occ, E));
+    return rank_select(ctx, P, E, k, cnt, idx, nullptr, Eout);
 }
 
 // ------------------------------------------------------------------ GA
@@ -673,13 +752,16 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
     const int32_t ne = (int32_t)std::min<int64_t>(std::max(prm->n_elite, 0), P);
     void* ws = nullptr;
     const size_t b_cum = round_up(P * 8, 256), b_el = round_up((ne + 1) * 4, 256);
-    GOAC_TRY(workspace(ctx, b_cum + b_el + 256, &ws));
+    const size_t b_cnt = round_up(((P + 1023) / 1024) * P * 4, 256);
+    GOAC_TRY(workspace(ctx, 2, b_cum + b_el + b_cnt + 256, &ws));
     uint64_t* cum = (uint64_t*)ws;
     int32_t* elite = (int32_t*)((char*)ws + b_cum);
-    int32_t* err = (int32_t*)((char*)ws + b_cum + b_el);
+    int32_t* cnt = (int32_t*)((char*)ws + b_cum + b_el);
+    int32_t* err = (int32_t*)((char*)ws + b_cum + b_el + b_cnt);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, err, 1);
-    hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, ne, cum, elite, err);
+    hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, cum, err);
     GOAC_CHECK_LAUNCH(ctx);
+    GOAC_TRY(rank_select(ctx, P, E_in, ne, cnt, nullptr, elite, nullptr));
     if (lds > 64 * 1024)
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_ga_child, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_ga_child, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
@@ -699,27 +781,40 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     const int n_inst = (int)ch->pbs.size();
     hipStream_t sm = ctx->stream;
     const bool mixed = ch->prec == GOAC_MIXED;
+    const int64_t C = ch->C;
     // per-chain offsets
-    ch->offs.resize(ch->C);
+    ch->offs.resize(C);
     int64_t tot = 0;
-    for (int64_t c = 0; c < ch->C; ++c) {
+    for (int64_t c = 0; c < C; ++c) {
         ch->offs[c] = tot;
         tot += ch->pbs[ch->inst_of[c]]->d.Mp;
     }
     ch->total = tot;
-    GOAC_TRY(dalloc(ctx, &ch->sc, ch->C));
-    GOAC_TRY(dalloc(ctx, &ch->insts, n_inst));
-    GOAC_TRY(dalloc(ctx, &ch->occ, tot));
-    GOAC_TRY(dalloc(ctx, &ch->perm, tot));
-    GOAC_TRY(dalloc(ctx, &ch->best, tot));
-    GOAC_TRY(dalloc(ctx, &ch->order, ch->C));
-    GOAC_TRY(dalloc(ctx, &ch->queue, 64));
-    GOAC_TRY(dalloc(ctx, &ch->d_offs, ch->C));
-    void* phi = nullptr;
-    GOAC_HIP(ctx, hipMalloc(&phi, (size_t)tot * (mixed ? 4 : 8) + 16));
-    ch->phi = phi;
-    // instance table
-    std::vector<McInst> insts(n_inst);
+    // one arena: the uploaded tables first (one copy), then the device-only state
+    ArenaPlan ap;
+    const size_t o_sc = ap.take(C * sizeof(ChainScalars));
+    const size_t o_in = ap.take(n_inst * sizeof(McInst));
+    const size_t o_of = ap.take(C * sizeof(int64_t));
+    const size_t o_or = ap.take(C * sizeof(int32_t));
+    const size_t o_q = ap.take(64 * sizeof(int32_t));
+    const size_t up_end = ap.end;
+    const size_t o_occ = ap.take(tot);
+    const size_t o_perm = ap.take(tot * sizeof(uint16_t));
+    const size_t o_best = ap.take(tot);
+    const size_t o_phi = ap.take(tot * (mixed ? 4 : 8));
+    GOAC_HIP(ctx, hipMalloc(&ch->arena, ap.end));
+    char* base = (char*)ch->arena;
+    ch->sc = (ChainScalars*)(base + o_sc);
+    ch->insts = (McInst*)(base + o_in);
+    ch->d_offs = (int64_t*)(base + o_of);
+    ch->order = (int32_t*)(base + o_or);
+    ch->queue = (int32_t*)(base + o_q);
+    ch->occ = (uint8_t*)(base + o_occ);
+    ch->perm = (uint16_t*)(base + o_perm);
+    ch->best = (uint8_t*)(base + o_best);
+    ch->phi = base + o_phi;
+    std::vector<char> host(up_end, 0);
+    McInst* insts = (McInst*)(host.data() + o_in);
     for (int i = 0; i < n_inst; ++i) {
         const ProblemDev& d = ch->pbs[i]->d;
         McInst& I = insts[i];
@@ -733,30 +828,24 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         ch->max_E = std::max(ch->max_E, d.E);
         ch->max_tab = std::max(ch->max_tab, tab_words(d.S, d.E));
     }
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->insts, insts.data(), n_inst * sizeof(McInst), hipMemcpyHostToDevice, sm));
-    // scalars
-    std::vector<ChainScalars> sc(ch->C);
-    for (int64_t c = 0; c < ch->C; ++c) {
-        ChainScalars& s = sc[c];
-        std::memset(&s, 0, sizeof(s));
-        s.inst = ch->inst_of[c];
-        s.chain_id = ch->chain_id[c];
-        s.off = ch->offs[c];
+    ChainScalars* sc = (ChainScalars*)(host.data() + o_sc);
+    for (int64_t c = 0; c < C; ++c) {
+        sc[c].inst = ch->inst_of[c];
+        sc[c].chain_id = ch->chain_id[c];
+        sc[c].off = ch->offs[c];
     }
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->sc, sc.data(), ch->C * sizeof(ChainScalars), hipMemcpyHostToDevice, sm));
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->d_offs, ch->offs.data(), ch->C * 8, hipMemcpyHostToDevice, sm));
+    std::memcpy(host.data() + o_of, ch->offs.data(), C * 8);
     // longest chains first (Mp as the cost), stable
-    std::vector<int32_t> order(ch->C);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    int32_t* order = (int32_t*)(host.data() + o_or);
+    std::iota(order, order + C, 0);
+    std::stable_sort(order, order + C, [&](int32_t a, int32_t b) {
         return ch->pbs[ch->inst_of[a]]->d.Mp > ch->pbs[ch->inst_of[b]]->d.Mp;
     });
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->order, order.data(), ch->C * 4, hipMemcpyHostToDevice, sm));
+    GOAC_HIP(ctx, hipMemcpyAsync(base, host.data(), up_end, hipMemcpyHostToDevice, sm));
     // composition check, setup and FP64 field, per instance
-    int32_t* err = nullptr;
-    GOAC_TRY(dalloc(ctx, &err, 1));
-    DevAllocs tmp;
-    tmp.ptrs.push_back(err);
+    void* sel = nullptr;
+    GOAC_TRY(workspace(ctx, 2, 256, &sel));
+    int32_t* err = (int32_t*)sel;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, sm, err, 1);
     for (int i = 0; i < n_inst; ++i) {
         goac_problem* pb = ch->pbs[i];
@@ -768,9 +857,11 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
                            d.msub, occ_i, err);
         hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)Ci), dim3(64), 0, sm, d.n, d.M, d.Mp, d.S, d.E, d.tab, d.mob,
                            d.msub, occ_i, ch->first_chain[i], ch->d_offs, ch->occ, ch->perm, ch->best);
-        double *Q = nullptr, *Phi = nullptr;
-        GOAC_HIP(ctx, hipMallocAsync((void**)&Q, (size_t)Ci * d.Mp * 8, sm));
-        GOAC_HIP(ctx, hipMallocAsync((void**)&Phi, (size_t)Ci * d.Mp * 8, sm));
+        const size_t qb = (size_t)round_up((int64_t)Ci * d.Mp * 8, 256);
+        void* ws = nullptr;
+        GOAC_TRY(workspace(ctx, 0, 2 * qb, &ws));
+        double* Q = (double*)ws;
+        double* Phi = (double*)((char*)ws + qb);
         GOAC_TRY(build_q64(ctx, Ci, d.n, d.M, d.Mp, d.E, occ_i, d.mob, d.charge, Q));
         GOAC_TRY(dgemm_nt(ctx, Ci, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr));
         if (mixed)
@@ -780,8 +871,6 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
             hipLaunchKernelGGL(k_chain_field<false>, dim3((unsigned)Ci), dim3(256), 0, sm, d.M, d.Mp, Q, Phi, d.h,
                                d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi);
         GOAC_CHECK_LAUNCH(ctx);
-        GOAC_HIP(ctx, hipFreeAsync(Q, sm));
-        GOAC_HIP(ctx, hipFreeAsync(Phi, sm));
     }
     int32_t herr = 0;
     GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, sm));
@@ -791,9 +880,8 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
 }
 
 static void chains_free(goac_chains* ch) {
-    void* ptrs[] = {ch->sc, ch->insts, ch->phi, ch->occ, ch->perm, ch->best, ch->order, ch->queue, ch->kT, ch->d_offs};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    if (ch->arena) (void)hipFree(ch->arena);
+    if (ch->kT) (void)hipFree(ch->kT);
 }
 
 extern "C" goac_status goac_chains_create(goac_problem* pb, int64_t C, const uint8_t* occ, goac_precision prec,

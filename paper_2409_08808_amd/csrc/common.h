@@ -73,6 +73,21 @@ __host__ __device__ inline uint64_t trial_hash(uint64_t t, uint32_t i, uint32_t 
     return splitmix64(splitmix64(t) ^ (((uint64_t)i << 33) | ((uint64_t)j << 1) | (acc & 1u)));
 }
 
+// ------------------------------------------------------------------ address spaces
+// Pointers read out of device memory (instance tables) are generic to the
+// compiler, which then emits flat loads; flat loads also count against the LDS
+// wait counter, so an LDS read after one stalls until the global load returns.
+// Casting to the global address space restores global loads.
+#define GOAC_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GOAC_GLOBAL T* gptr(const T* p) {
+    return (const GOAC_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ GOAC_GLOBAL T* gptr_rw(T* p) {
+    return (GOAC_GLOBAL T*)p;
+}
+
 // ------------------------------------------------------------------ device structs
 
 // Sublattice tables of a problem, laid out as int32 words:
@@ -143,13 +158,14 @@ struct McInst {
 }  // namespace goac
 
 // ------------------------------------------------------------------ host objects
+constexpr int kWsSlots = 3;   // scratch slots: 0 kernels' operands, 1 GEMM partials, 2 selection
 struct goac_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cus = 256;
     std::string err;
-    void* ws = nullptr;     // scratch, grown on demand
-    size_t ws_size = 0;
+    void* ws[kWsSlots] = {nullptr, nullptr, nullptr};  // scratch, grown on demand
+    size_t ws_size[kWsSlots] = {0, 0, 0};
 };
 
 struct goac_problem {
@@ -163,6 +179,7 @@ struct goac_problem {
     int32_t* spos_inv = nullptr;     // M: index of position k in spos
     int32_t* fixed_idx = nullptr;    // fixed sites
     int32_t n_fixed = 0;
+    void* arena = nullptr;           // one allocation holding every device array
 };
 
 struct goac_chains {
@@ -181,7 +198,7 @@ struct goac_chains {
     uint8_t* best = nullptr;          // total
     int32_t* order = nullptr;         // C, longest chains first
     int32_t* queue = nullptr;         // work counter of the persistent sweep
-    int32_t* due = nullptr;           // C + 1: chains due for re-anchoring
+    void* arena = nullptr;            // one allocation holding every array below
     double* kT = nullptr;             // device kT table
     size_t kT_cap = 0;
     int64_t* d_offs = nullptr;        // C element offsets (device)
@@ -241,7 +258,7 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
                       const int32_t* mob, const double* charge, double* Q);
 
 // scratch memory of a context (grown, never shrunk)
-goac_status workspace(goac_ctx* ctx, size_t bytes, void** out = nullptr);
+goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
 
 // kernels shared across translation units
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,

@@ -54,6 +54,9 @@ double norm3(const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2
 __global__ void k_ewald_real(int64_t n, const double* __restrict__ frac, const double* __restrict__ A9,
                              const double* __restrict__ trans, int32_t n_trans, double alpha, double rcut,
                              double ke, double cst, double self, double* __restrict__ V) {
+    extern __shared__ double s_tr[];
+    for (int m = threadIdx.x; m < 3 * n_trans; m += blockDim.x) s_tr[m] = trans[m];
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = blockIdx.y;
     if (j >= n) return;
@@ -70,7 +73,7 @@ __global__ void k_ewald_real(int64_t n, const double* __restrict__ frac, const d
     const double rc2 = rcut * rcut;
     double s = 0.0;
     for (int m = 0; m < n_trans; ++m) {
-        const double x = r[0] + trans[3 * m], y = r[1] + trans[3 * m + 1], z = r[2] + trans[3 * m + 2];
+        const double x = r[0] + s_tr[3 * m], y = r[1] + s_tr[3 * m + 1], z = r[2] + s_tr[3 * m + 2];
         const double d2 = x * x + y * y + z * z;
         if (d2 < rc2 && d2 > 0.0) {
             const double dd = sqrt(d2);
@@ -169,7 +172,7 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
     const size_t b_tr = round_up(trans.size() * 8 + 8, 256), b_G = round_up(G.size() * 8 + 8, 256);
     const size_t b_A = 256, b_T = (size_t)n * ld * 8;
     void* ws = nullptr;
-    goac_status st = workspace(ctx, b_frac + b_pos + b_tr + b_G + b_A + b_T, &ws);
+    goac_status st = workspace(ctx, 0, b_frac + b_pos + b_tr + b_G + b_A + b_T, &ws);
     if (st != GOAC_OK) return st;
     char* p = (char*)ws;
     double* d_frac = (double*)p; p += b_frac;
@@ -192,8 +195,10 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
     const double cst = -ke * kPi / (c.vol * alpha * alpha);
     const double self = ke * 2.0 * alpha / std::sqrt(kPi);
     {
-        dim3 grid((unsigned)((n + 127) / 128), (unsigned)n);
-        hipLaunchKernelGGL(k_ewald_real, grid, dim3(128), 0, ctx->stream, n, d_frac, d_A, d_tr,
+        const size_t lds_tr = trans.size() * sizeof(double);
+        if (lds_tr > 60 * 1024) return fail(ctx, GOAC_EINVAL, "build_ewald: real-space cutoff spans too many cells");
+        dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
+        hipLaunchKernelGGL(k_ewald_real, grid, dim3(256), lds_tr, ctx->stream, n, d_frac, d_A, d_tr,
                            (int32_t)(trans.size() / 3), alpha, rcut, ke, cst, self, V);
         GOAC_CHECK_LAUNCH(ctx);
     }

@@ -52,10 +52,9 @@ __global__ void k_init(int64_t n, int32_t S, int32_t E, const int32_t* __restric
 // ------------------------------------------------------------------ GA: selection tables
 // One workgroup: E_max, integer roulette weights round((E_max - E_p) 2^30) and
 // their inclusive prefix sums (exact, so the order of the additions does not
-// matter), and the n_elite smallest (E, index) pairs by rank counting.
-__global__ __launch_bounds__(1024) void k_ga_prep(int64_t P, const double* __restrict__ E, int32_t n_elite,
-                                                  uint64_t* __restrict__ cum, int32_t* __restrict__ elite,
-                                                  int32_t* __restrict__ err) {
+// matter). The elites come from rank_select.
+__global__ __launch_bounds__(1024) void k_ga_prep(int64_t P, const double* __restrict__ E,
+                                                  uint64_t* __restrict__ cum, int32_t* __restrict__ err) {
     __shared__ double s_red[1024];
     __shared__ uint64_t s_tot[1024];
     const int tid = threadIdx.x;
@@ -95,15 +94,6 @@ __global__ __launch_bounds__(1024) void k_ga_prep(int64_t P, const double* __res
     __syncthreads();
     const uint64_t base = s_tot[tid];
     for (int64_t p = lo; p < hi; ++p) cum[p] += base;
-    for (int64_t p = tid; p < P; p += nt) {
-        const double ep = E[p];
-        int64_t rank = 0;
-        for (int64_t q = 0; q < P && rank < n_elite; ++q) {
-            const double eq = E[q];
-            rank += (eq < ep || (eq == ep && q < p)) ? 1 : 0;
-        }
-        if (rank < n_elite) elite[rank] = (int32_t)p;
-    }
 }
 
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
@@ -247,21 +237,57 @@ __global__ __launch_bounds__(64) void k_ga_child(
     for (int f = lane; f < n_fixed; f += 64) out[fixed_idx[f]] = ref_occ[fixed_idx[f]];
 }
 
-// ------------------------------------------------------------------ top-k by rank counting
-__global__ void k_topk_select(int64_t P, int32_t k, const double* __restrict__ E, int64_t* __restrict__ idx,
-                              double* __restrict__ Eout) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ------------------------------------------------------------------ ranking
+// rank(p) = #{q : (E_q, q) < (E_p, p)} (a strict total order, so ranks are
+// distinct); the k smallest ranks are the k lowest configurations. Partial
+// counts over segments of q run in parallel (one thread per (p, segment), the
+// segment staged in LDS), then are summed in segment order.
+constexpr int RK_SEG = 1024;
+
+__global__ __launch_bounds__(256) void k_rank_partial(int64_t P, const double* __restrict__ E,
+                                                      int32_t* __restrict__ cnt) {
+    __shared__ double tile[RK_SEG];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t seg = blockIdx.y;
+    const int64_t b0 = seg * RK_SEG;
+    const int len = (int)(P - b0 < RK_SEG ? P - b0 : RK_SEG);
+    for (int x = threadIdx.x; x < len; x += 256) tile[x] = E[b0 + x];
+    __syncthreads();
     if (p >= P) return;
     const double ep = E[p];
-    int64_t rank = 0;
-    for (int64_t q = 0; q < P && rank < k; ++q) {
-        const double eq = E[q];
-        rank += (eq < ep || (eq == ep && q < p)) ? 1 : 0;
+    int c = 0;
+    for (int x = 0; x < len; ++x) {
+        const double eq = tile[x];
+        c += (eq < ep || (eq == ep && b0 + x < p)) ? 1 : 0;
     }
-    if (rank < k) {
-        idx[rank] = p;
-        Eout[rank] = ep;
+    cnt[seg * P + p] = c;
+}
+
+// idx[rank] = p (int64 or int32 output) and Eout[rank] = E_p for rank < k
+__global__ void k_rank_finish(int64_t P, int32_t n_seg, int32_t k, const double* __restrict__ E,
+                              const int32_t* __restrict__ cnt, int64_t* __restrict__ idx64,
+                              int32_t* __restrict__ idx32, double* __restrict__ Eout) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int64_t r = 0;
+    for (int s = 0; s < n_seg; ++s) r += cnt[(int64_t)s * P + p];
+    if (r < k) {
+        if (idx64) idx64[r] = p;
+        if (idx32) idx32[r] = (int32_t)p;
+        if (Eout) Eout[r] = E[p];
     }
+}
+
+goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, int32_t* cnt_scratch,
+                        int64_t* idx64, int32_t* idx32, double* Eout) {
+    if (k <= 0 || P <= 0) return GOAC_OK;
+    const int32_t n_seg = (int32_t)((P + RK_SEG - 1) / RK_SEG);
+    dim3 g1((unsigned)((P + 255) / 256), (unsigned)n_seg);
+    hipLaunchKernelGGL(k_rank_partial, g1, dim3(256), 0, ctx->stream, P, E, cnt_scratch);
+    hipLaunchKernelGGL(k_rank_finish, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, n_seg, k, E,
+                       cnt_scratch, idx64, idx32, Eout);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
 }
 
 }  // namespace goac

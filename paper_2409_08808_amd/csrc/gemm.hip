@@ -14,56 +14,73 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ FP64 NT GEMM
+// C = alpha A B^T + beta C, A: M x K (lda), B: N x K (ldb), FP64.
 // Tile 64 x 64 x 16, 256 threads = 4 waves in a 2 x 2 grid, each wave a 32 x 32
-// block of four 16 x 16 MFMA accumulators. Operands are staged k-major in LDS so
-// every lane's MFMA operand is one 8-byte LDS read. Rows beyond M (or *M_dev) and
-// columns beyond N are skipped; K is zero-padded.
+// block of four 16 x 16 MFMA accumulators. Operands are staged k-major in two LDS
+// buffers; the next K-slice is loaded into registers while the matrix cores work
+// on the current one (one barrier per slice). Rows beyond M (or *M_dev) and
+// columns beyond N are skipped; K is zero-padded. With split-K (gridDim.z > 1)
+// each z-slice writes its partial product to `part`, reduced in slice order by
+// k_dgemm_reduce (deterministic).
 constexpr int DG_BM = 64, DG_BN = 64, DG_BK = 16;
 
 __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                                   int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                   double* __restrict__ C, int64_t ldc, double alpha, double beta,
-                                                  const int32_t* __restrict__ M_dev) {
-    __shared__ double As[DG_BK][DG_BM + 2];
-    __shared__ double Bs[DG_BK][DG_BN + 2];
+                                                  const int32_t* __restrict__ M_dev, int64_t k_per_split,
+                                                  double* __restrict__ part) {
+    __shared__ double As[2][DG_BK][DG_BM + 2];
+    __shared__ double Bs[2][DG_BK][DG_BN + 2];
     if (M_dev) M = *M_dev;
     const int64_t m0 = (int64_t)blockIdx.y * DG_BM;
     const int64_t n0 = (int64_t)blockIdx.x * DG_BN;
     if (m0 >= M) return;
+    const int64_t kbeg = (int64_t)blockIdx.z * k_per_split;
+    const int64_t kend = kbeg + k_per_split < K ? kbeg + k_per_split : K;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     f64x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // loader mapping: each thread moves 4 consecutive k of one row
+    // loader mapping: each thread moves 4 consecutive k of one row of A and of B
     const int lr = tid >> 2;          // 0..63
     const int lk = (tid & 3) * 4;     // 0, 4, 8, 12
-    for (int64_t k0 = 0; k0 < K; k0 += DG_BK) {
-        {
-            const int64_t gm = m0 + lr;
-            const int64_t gn = n0 + lr;
+    const int64_t gm = m0 + lr, gn = n0 + lr;
+    const double* pa = A + gm * lda;
+    const double* pb = B + gn * ldb;
+    double ra[4], rb[4];
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t gk = k0 + lk + q;
-                As[lk + q][lr] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
-                Bs[lk + q][lr] = (gn < N && gk < K) ? B[gn * ldb + gk] : 0.0;
-            }
+        for (int q = 0; q < 4; ++q) {
+            const int64_t gk = k0 + lk + q;
+            ra[q] = (gm < M && gk < kend) ? pa[gk] : 0.0;
+            rb[q] = (gn < N && gk < kend) ? pb[gk] : 0.0;
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    int buf = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += DG_BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[buf][lk + q][lr] = ra[q];
+            Bs[buf][lk + q][lr] = rb[q];
         }
         __syncthreads();
+        if (k0 + DG_BK < kend) fetch(k0 + DG_BK);
 #pragma unroll
         for (int ks = 0; ks < DG_BK; ks += 4) {
             const int kk = ks + (lane >> 4);
-            const double a0 = As[kk][wm * 32 + (lane & 15)];
-            const double a1 = As[kk][wm * 32 + 16 + (lane & 15)];
-            const double b0 = Bs[kk][wn * 32 + (lane & 15)];
-            const double b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
+            const double a0 = As[buf][kk][wm * 32 + (lane & 15)];
+            const double a1 = As[buf][kk][wm * 32 + 16 + (lane & 15)];
+            const double b0 = Bs[buf][kk][wn * 32 + (lane & 15)];
+            const double b1 = Bs[buf][kk][wn * 32 + 16 + (lane & 15)];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
-        __syncthreads();
+        buf ^= 1;
     }
     // FP64 16x16 accumulators interleave rows: D[row = lane / 16 + 4 v][col = lane % 16]
 #pragma unroll
@@ -72,24 +89,59 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t 
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t gm = m0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-                const int64_t gn = n0 + wn * 32 + b * 16 + (lane & 15);
-                if (gm < M && gn < N) {
-                    double* c = C + gm * ldc + gn;
-                    const double val = alpha * acc[a][b][v];
-                    *c = (beta == 0.0) ? val : val + beta * *c;
+                const int64_t r = m0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+                const int64_t cix = n0 + wn * 32 + b * 16 + (lane & 15);
+                if (r < M && cix < N) {
+                    if (part) {
+                        part[((int64_t)blockIdx.z * M + r) * N + cix] = acc[a][b][v];
+                    } else {
+                        double* c = C + r * ldc + cix;
+                        const double val = alpha * acc[a][b][v];
+                        *c = (beta == 0.0) ? val : val + beta * *c;
+                    }
                 }
             }
+}
+
+// C = alpha sum_z part[z] + beta C, slices summed in order
+__global__ void k_dgemm_reduce(int64_t M, int64_t N, int32_t splits, const double* __restrict__ part,
+                               double* __restrict__ C, int64_t ldc, double alpha, double beta) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t r = idx / N, c = idx - r * N;
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    double* o = C + r * ldc + c;
+    const double val = alpha * s;
+    *o = (beta == 0.0) ? val : val + beta * *o;
 }
 
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
                      const int32_t* M_dev) {
     if (M <= 0 || N <= 0) return GOAC_OK;
-    dim3 grid((unsigned)((N + DG_BN - 1) / DG_BN), (unsigned)((M + DG_BM - 1) / DG_BM));
-    hipLaunchKernelGGL(k_dgemm_nt, grid, dim3(256), 0, ctx->stream, M, N, K, A, lda, B, ldb, C, ldc,
-                       alpha, beta, M_dev);
+    const int64_t tiles = ((N + DG_BN - 1) / DG_BN) * ((M + DG_BM - 1) / DG_BM);
+    // split K when the tile grid leaves most compute units idle and K is long
+    int splits = 1;
+    const int64_t want = 2 * (int64_t)ctx->num_cus;
+    while (!M_dev && tiles * splits < want && K / (splits * 2) >= 512 && splits < 32) splits *= 2;
+    const int64_t kps = round_up((K + splits - 1) / splits, DG_BK);
+    double* part = nullptr;
+    if (splits > 1) {
+        void* w = nullptr;
+        goac_status st = workspace(ctx, 1, (size_t)splits * M * N * sizeof(double), &w);
+        if (st != GOAC_OK) return st;
+        part = (double*)w;
+    }
+    dim3 grid((unsigned)((N + DG_BN - 1) / DG_BN), (unsigned)((M + DG_BM - 1) / DG_BM), (unsigned)splits);
+    hipLaunchKernelGGL(k_dgemm_nt, grid, dim3(256), 0, ctx->stream, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta,
+                       M_dev, kps, part);
     GOAC_CHECK_LAUNCH(ctx);
+    if (splits > 1) {
+        hipLaunchKernelGGL(k_dgemm_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, ctx->stream, M, N,
+                           splits, part, C, ldc, alpha, beta);
+        GOAC_CHECK_LAUNCH(ctx);
+    }
     return GOAC_OK;
 }
 
@@ -219,15 +271,21 @@ __global__ void k_build_q64(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t
     out[idx] = v;
 }
 
-// E[p] = E_ff + sum_k q_k (h_k + Phi_k / 2), k in order
-__global__ void k_pop_fp64_finalize(int64_t P, int32_t M, int32_t Mp, const double* __restrict__ Q,
-                                    const double* __restrict__ Phi, const double* __restrict__ h, double E_ff,
-                                    double* __restrict__ E) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// E[p] = E_ff + sum_k q_k (h_k + Phi_k / 2): one wavefront per row, lanes stride
+// over k, fixed-order butterfly sum (deterministic)
+__global__ __launch_bounds__(256) void k_pop_fp64_finalize(int64_t P, int32_t M, int32_t Mp,
+                                                           const double* __restrict__ Q,
+                                                           const double* __restrict__ Phi,
+                                                           const double* __restrict__ h, double E_ff,
+                                                           double* __restrict__ E) {
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (p >= P) return;
     double s = 0.0;
-    for (int k = 0; k < M; ++k) s += Q[p * Mp + k] * (h[k] + 0.5 * Phi[p * Mp + k]);
-    E[p] = E_ff + s;
+    for (int k = lane; k < M; k += 64) s += Q[p * Mp + k] * (h[k] + 0.5 * Phi[p * Mp + k]);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) E[p] = E_ff + s;
 }
 
 goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
@@ -246,7 +304,7 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
     const size_t dq_bytes = (size_t)P * d.Mp * sizeof(__hip_bfloat16);
     const size_t part_bytes = (size_t)P * n_tiles * sizeof(double);
     void* ws = nullptr;
-    goac_status st = workspace(ctx, round_up(dq_bytes, 256) + part_bytes, &ws);
+    goac_status st = workspace(ctx, 0, round_up(dq_bytes, 256) + part_bytes, &ws);
     if (st != GOAC_OK) return st;
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
     double* part = (double*)((char*)ws + round_up(dq_bytes, 256));
@@ -275,14 +333,14 @@ goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, doubl
     const ProblemDev& d = pb->d;
     const size_t qb = round_up((size_t)P * d.Mp * sizeof(double), 256);
     void* ws = nullptr;
-    goac_status st = workspace(ctx, 2 * qb, &ws);
+    goac_status st = workspace(ctx, 0, 2 * qb, &ws);
     if (st != GOAC_OK) return st;
     double* Q = (double*)ws;
     double* Phi = (double*)((char*)ws + qb);
     GOAC_TRY_(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q));
     st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr);
     if (st != GOAC_OK) return st;
-    hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, d.M,
+    hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M,
                        d.Mp, Q, Phi, d.h, d.E_ff, E);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;

@@ -86,22 +86,24 @@ __device__ void anchor_chain(const McInst& I, const uint8_t* occ, const uint8_t*
                              const double* phibar, float* phi, double* scr, double& E_out, double& eps_out,
                              float& phib_out) {
     const int M = I.M;
+    const GOAC_GLOBAL double* V64 = gptr(I.V64);
+    const GOAC_GLOBAL double* hv = gptr(I.h);
     double esum = 0.0, pmax = 0.0, amax = 0.0;
     for (int k0 = 0; k0 < M; k0 += WG) {
         const int k = k0 + threadIdx.x;
         const bool ok = k < M;
-        double acc = ok ? I.h[k] : 0.0;
+        double acc = ok ? hv[k] : 0.0;
         double aab = ok ? fabs(acc) : 0.0;
         for (int l = 0; l < M; ++l) {
             const double ql = chg[occ[l]];
             if (ok) {
-                const double v = I.V64[(int64_t)l * I.Mp + k];
+                const double v = V64[(int64_t)l * I.Mp + k];
                 acc += v * ql;
                 aab += fabs(v * ql);
             }
         }
         if (ok) {
-            const double hk = I.h[k];
+            const double hk = hv[k];
             const double qk = chg[occ[k]];
             esum += qk * (acc + hk);
             const float p = (float)(acc - phibar[msub[k]]);
@@ -157,24 +159,29 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
         const McInst I = a.insts[inst];
         const int M = I.M, Mp = I.Mp, S = I.S, E = I.E;
         const int64_t off = sc->off;
-        T* gphi = reinterpret_cast<T*>(a.phi) + off;
-        uint8_t* gocc = a.occ + off;
-        uint16_t* gperm = a.perm + off;
-        uint8_t* gbest = a.best + off;
+        GOAC_GLOBAL T* gphi = gptr_rw(reinterpret_cast<T*>(a.phi) + off);
+        GOAC_GLOBAL uint8_t* gocc = gptr_rw(a.occ + off);
+        GOAC_GLOBAL uint16_t* gperm = gptr_rw(a.perm + off);
+        GOAC_GLOBAL uint8_t* gbest = gptr_rw(a.best + off);
+        const GOAC_GLOBAL double* V64 = gptr(I.V64);
+        const GOAC_GLOBAL float* V32 = gptr(I.V32);
+        const GOAC_GLOBAL double* diag = gptr(I.diag);
+        const GOAC_GLOBAL float* rowmax = gptr(I.rowmax);
+        const GOAC_GLOBAL double* hv = gptr(I.h);
         const int ntab = tab_words(S, E);
         // ---- load the chain into LDS
         for (int k = tid; k < Mp; k += WG) {
             phi[k] = gphi[k];
             occ[k] = gocc[k];
-            msub[k] = I.msub[k];
+            msub[k] = gptr(I.msub)[k];
             const uint16_t p = gperm[k];
             perm[k] = p;
         }
-        for (int k = tid; k < ntab; k += WG) tab[k] = I.tab[k];
-        for (int k = tid; k < E; k += WG) chg[k] = I.charge[k];
+        for (int k = tid; k < ntab; k += WG) tab[k] = gptr(I.tab)[k];
+        for (int k = tid; k < E; k += WG) chg[k] = gptr(I.charge)[k];
         __syncthreads();
         for (int k = tid; k < M; k += WG) where[perm[k]] = (uint16_t)k;
-        if (MIXED && tid < S) s_phibar[tid] = I.phibar[tid];
+        if (MIXED && tid < S) s_phibar[tid] = gptr(I.phibar)[tid];
         __syncthreads();
         const int32_t* subsize = tab + 2;
         const int32_t* suboff = subsize + S;
@@ -189,31 +196,39 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
         float phib = sc->phibound;
         uint32_t since = sc->since_anchor;
         int status = sc->status;
-        const double* kTrow = a.kT + (int64_t)sc->row * a.n_blocks;
+        const GOAC_GLOBAL double* kTrow = gptr(a.kT + (int64_t)sc->row * a.n_blocks);
         const uint32_t chain_id = sc->chain_id;
         const uint32_t w3 = (I.instance << 8) | TAG_MC;
         uint64_t hsum = 0;
         int parity = 0;
 
+        // temperature block of the window start; a window of WG <= block_len trials
+        // crosses at most one block boundary (otherwise each lane divides)
+        uint64_t blk0 = t / a.block_len;
+        uint64_t bnd = (blk0 + 1) * a.block_len;
+        const bool wide_blocks = a.block_len >= (uint64_t)WG;
+        const uint64_t nb1 = (uint64_t)(a.n_blocks - 1);
         while (t < t_end) {
             const uint64_t tl = t + (uint64_t)tid;
             const bool valid = tl < t_end;
-            // temperature: the window straddles at most one block boundary when WG <= block_len
             double kT;
-            {
+            if (wide_blocks) {
+                const double kT0 = kTrow[blk0 < nb1 ? blk0 : nb1];
+                const double kT1 = kTrow[blk0 + 1 < nb1 ? blk0 + 1 : nb1];
+                kT = tl >= bnd ? kT1 : kT0;
+            } else {
                 const uint64_t blk = tl / a.block_len;
-                kT = kTrow[blk < (uint64_t)a.n_blocks ? blk : (uint64_t)(a.n_blocks - 1)];
+                kT = kTrow[blk < nb1 ? blk : nb1];
             }
             const u32x4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), chain_id, w3, a.seed);
             const int i = (int)mulshift(r.x, (uint32_t)M);
-            const int s = msub[i];
+            const int s = S == 1 ? 0 : msub[i];
             const int sa = occ[i];
             const int na = cnt[s * E + sa];
             const int csz = subsize[s] - na;
             int j = i;
             bool stop = false, unsure = false;
             double d = 0.0, dE = 0.0;
-            const double u = unit_open(r.z, r.w);
             if (valid && csz > 0) {
                 const int k = (int)mulshift(r.y, (uint32_t)csz);
                 const int idx = k < offs[s * E + sa] ? k : k + na;
@@ -221,24 +236,31 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                 const int sb = occ[j];
                 d = chg[sb] - chg[sa];
                 const double phi_i = (double)phi[i], phi_j = (double)phi[j];
-                const double Vii = I.diag[i], Vjj = I.diag[j];
-                const double Vij = I.V64[(int64_t)i * Mp + j];
+                const double Vii = diag[i], Vjj = diag[j];
+                const double Vij = V64[(int64_t)i * Mp + j];
                 dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
-                const double L = -kT * log(u);
-                const double m = 1e-10 * (fabs(L) + kT);
-                if (MIXED) {
+                // Metropolis threshold L = -kT ln u, first in FP32 from the top 24 bits
+                // of u: |L32 - L| <= m32 (u32 within 2^-25 of u, log within 2^-20 relative);
+                // tests closer than m32 to the threshold use the exact FP64 rule
+                const uint32_t ub = r.z >> 8;
+                const float u32 = ((float)ub + 0.5f) * 0x1p-24f;
+                const float lg = __logf(u32);
+                const float kTf = (float)kT;
+                const double L32 = (double)(-kTf * lg);
+                const double m32 = ub < 2 ? INFINITY : (double)(kTf * (0x1p-24f / u32 + 0x1p-20f * (1.0f - lg)));
+                if constexpr (MIXED) {
                     const double e = d != 0.0 ? 2.0 * fabs(d) * eps + kMargin : 0.0;
                     const double hi = dE + e, lo = dE - e;
-                    const bool sure_acc = (hi <= 0.0) || (hi < L - m);
-                    const bool sure_rej = (lo > 0.0) && (lo > L + m);
+                    const bool sure_acc = (hi <= 0.0) || (hi - L32 < -m32);
+                    const bool sure_rej = (lo > 0.0) && (lo - L32 > m32);
                     unsure = !sure_acc && !sure_rej;
                     stop = sure_acc || unsure;
                 } else {
                     bool acc;
                     if (dE <= 0.0) acc = true;
-                    else if (dE < L - m) acc = true;
-                    else if (dE > L + m) acc = false;
-                    else acc = u < exp(-dE / kT);
+                    else if (dE - L32 < -m32) acc = true;
+                    else if (dE - L32 > m32) acc = false;
+                    else acc = unit_open(r.z, r.w) < exp(-dE / kT);
                     stop = acc;
                 }
             }
@@ -260,11 +282,12 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
             if (TRACE && valid && tid < f) hsum += trial_hash(tl, (uint32_t)i, (uint32_t)j, 0u);
             if (f >= nvalid) {
                 t += (uint64_t)nvalid;
+                while (t >= bnd) { ++blk0; bnd += a.block_len; }
                 continue;
             }
             if (tid == f) {
                 s_b.i = i; s_b.j = j; s_b.unsure = unsure ? 1 : 0;
-                s_b.d = d; s_b.dE = dE; s_b.u = u; s_b.kT = kT;
+                s_b.d = d; s_b.dE = dE; s_b.u = unit_open(r.z, r.w); s_b.kT = kT;
             }
             __syncthreads();
             const int bi = s_b.i, bj = s_b.j;
@@ -275,10 +298,10 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                 // exact FP64 difference phi_i - phi_j from the occupation
                 double part = 0.0;
                 for (int k = tid; k < M; k += WG)
-                    part += (I.V64[(int64_t)bi * Mp + k] - I.V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
-                const double diff = wg_sum<WG>(part, s_scr) + (I.h[bi] - I.h[bj]);
-                const double Vii = I.diag[bi], Vjj = I.diag[bj];
-                const double Vij = I.V64[(int64_t)bi * Mp + bj];
+                    part += (V64[(int64_t)bi * Mp + k] - V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
+                const double diff = wg_sum<WG>(part, s_scr) + (hv[bi] - hv[bj]);
+                const double Vii = diag[bi], Vjj = diag[bj];
+                const double Vij = V64[(int64_t)bi * Mp + bj];
                 bdE = bd * diff + 0.5 * bd * bd * (Vii + Vjj - 2.0 * Vij);
                 accf = (bdE <= 0.0) || (s_b.u < exp(-bdE / s_b.kT));
                 ++n_fb;
@@ -287,14 +310,14 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
             if (accf) {
                 if (bd != 0.0) {
                     const T dd = (T)bd;
-                    const T* Vi;
-                    const T* Vj;
-                    if (MIXED) {
-                        Vi = reinterpret_cast<const T*>(I.V32 + (int64_t)bi * Mp);
-                        Vj = reinterpret_cast<const T*>(I.V32 + (int64_t)bj * Mp);
+                    const GOAC_GLOBAL T* Vi;
+                    const GOAC_GLOBAL T* Vj;
+                    if constexpr (MIXED) {
+                        Vi = V32 + (int64_t)bi * Mp;
+                        Vj = V32 + (int64_t)bj * Mp;
                     } else {
-                        Vi = reinterpret_cast<const T*>(I.V64 + (int64_t)bi * Mp);
-                        Vj = reinterpret_cast<const T*>(I.V64 + (int64_t)bj * Mp);
+                        Vi = V64 + (int64_t)bi * Mp;
+                        Vj = V64 + (int64_t)bj * Mp;
                     }
                     bool over = false;
                     constexpr int VEC = MIXED ? 4 : 2;
@@ -344,7 +367,7 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                     }
                     // two fused multiply-adds per element, each rounding <= u |intermediate|,
                     // plus the FP32 rounding of the two V entries
-                    const double rmi = (double)I.rowmax[bi], rmj = (double)I.rowmax[bj];
+                    const double rmi = (double)rowmax[bi], rmj = (double)rowmax[bj];
                     const double ad = fabs(bd);
                     eps += kU32 * (2.0 * (double)phib + ad * (rmi + 2.0 * (rmi + rmj))) * 1.0001;
                     if (!(eps < 1e3)) status = 1;
@@ -363,6 +386,7 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                 }
             }
             t += (uint64_t)(f + 1);
+            while (t >= bnd) { ++blk0; bnd += a.block_len; }
         }
         // ---- write the chain back
         __syncthreads();
