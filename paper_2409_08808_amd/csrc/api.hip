@@ -21,6 +21,8 @@ __global__ void k_ga_child(int64_t, int32_t, int32_t, int32_t, const int32_t*, c
                            const uint8_t*, const uint64_t*, const int32_t*, int32_t, uint64_t, uint32_t, double,
                            uint8_t*);
 goac_status rank_select(goac_ctx*, int64_t, const double*, int32_t, int32_t*, int64_t*, int32_t*, double*);
+goac_status anchor_batched(goac_ctx*, goac_chains*, int, uint32_t);
+constexpr int kInlineAnchorMaxMp = 1024;
 
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
     if (slot < 0 || slot >= kWsSlots) return fail(ctx, GOAC_EINVAL, "workspace slot");
@@ -1007,8 +1009,7 @@ extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm)
         ch->kT_cap = nkT;
     }
     GOAC_HIP(ctx, hipMemcpyAsync(ch->kT, prm->kT_host, nkT * 8, hipMemcpyHostToDevice, ctx->stream));
-    // the persistent grid pulls chains from a counter that starts at zero
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+    // the persistent grid pulls chains from a counter that starts at zero (reset before each launch)
     const int wg = prm->variant == 64 || prm->variant == 256 ? prm->variant : (ch->max_Mp >= 2048 ? 256 : 64);
     if (prm->variant != 0 && prm->variant != 64 && prm->variant != 256)
         return fail(ctx, GOAC_EINVAL, "mc_sweep: variant must be 0, 64 or 256");
@@ -1037,7 +1038,23 @@ extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm)
     a.lds_phi_bytes = (int32_t)phi_bytes;
     a.Mp_max = ch->max_Mp;
     a.tab_max = (int32_t)round_up(ch->max_tab, 4);
-    return mc_launch(ctx, a, mixed, (prm->flags & GOAC_MC_TRACE_HASH) != 0, wg, lds, grid);
+    const bool trace = (prm->flags & GOAC_MC_TRACE_HASH) != 0;
+    // MIXED: small cells re-anchor inside the kernel; large cells run in chunks of
+    // 8 x reanchor_every trials with a batched FP64 anchor of the due chains after each
+    a.inline_anchor = (mixed && ch->max_Mp > kInlineAnchorMaxMp) ? 0 : 1;
+    a.pad_ = 0;
+    if (a.inline_anchor) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+        return mc_launch(ctx, a, mixed, trace, wg, lds, grid);
+    }
+    const uint64_t chunk = (uint64_t)prm->reanchor_every * 8;
+    for (uint64_t done = 0; done < prm->n_trials; done += chunk) {
+        a.n_trials = std::min<uint64_t>(chunk, prm->n_trials - done);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+        GOAC_TRY(mc_launch(ctx, a, mixed, trace, wg, lds, grid));
+        for (size_t i = 0; i < ch->pbs.size(); ++i) GOAC_TRY(anchor_batched(ctx, ch, (int)i, (uint32_t)prm->reanchor_every));
+    }
+    return GOAC_OK;
 }
 
 extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats) {

@@ -146,86 +146,144 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 }
 
 // ------------------------------------------------------------------ bf16 hi+lo population GEMM
-// Phi[p][n] = sum_k dQ[p][k] (Vhi[n][k] + Vlo[n][k])  (V symmetric, so rows of V
-// serve as columns), FP32 accumulation. Epilogue per output tile:
-//   part[p][tile_n] = sum_{n in tile} dQ[p][n] (ht[n] + Phi[p][n] / 2)   (FP64)
-// Tile 64 (p) x 64 (n) x 64 (k), 256 threads = 2 x 2 waves, each wave one 32 x 32
-// accumulator fed by both the hi and the lo operand.
-constexpr int PB_BM = 64, PB_BN = 64, PB_BK = 64, PB_LD = PB_BK + 8;
+// Phi[p][n] = sum_k dQ[p][k] (Vhi[n][k] + Vlo[n][k]) (V is symmetric, so its rows
+// serve as columns), bf16 inputs, FP32 accumulation on v_mfma_f32_32x32x16_bf16.
+// Fused epilogue per output tile, in FP64 (linear in Phi, so K may be split):
+//   part[p][t] = sum_{n in tile} dQ[p][n] (ht[n] [first K slice only] + Phi_slice[p][n] / 2)
+// Tile 128 (p) x 128 (n) x 32 (k), 256 threads = 2 x 2 waves, each wave 64 x 64 =
+// 2 x 2 accumulators, each fed by the hi and the lo operand: 8 MFMAs per 6 LDS
+// operand reads. The next K stage is fetched into registers while the matrix
+// cores work on the current one; double-buffered LDS, one barrier per stage.
+constexpr int PB_BM = 128, PB_BN = 128, PB_BK = 32, PB_LD = PB_BK + 8;
 
-__global__ __launch_bounds__(256) void k_pop_bf16(int64_t P, int32_t Mp, const __hip_bfloat16* __restrict__ dQ,
+__global__ __launch_bounds__(256) void k_pop_bf16(int64_t P, int32_t M, int32_t Mp,
+                                                  const __hip_bfloat16* __restrict__ dQ,
                                                   const __hip_bfloat16* __restrict__ Vhi,
                                                   const __hip_bfloat16* __restrict__ Vlo,
                                                   const double* __restrict__ ht, double* __restrict__ part,
-                                                  int32_t n_tiles) {
-    __shared__ __align__(16) __hip_bfloat16 As[PB_BM][PB_LD];
-    __shared__ __align__(16) __hip_bfloat16 Hs[PB_BN][PB_LD];
-    __shared__ __align__(16) __hip_bfloat16 Ls[PB_BN][PB_LD];
-    __shared__ double red[PB_BM][PB_BN / 32 * 1 + 1];
+                                                  int32_t n_tiles_total, int32_t k_per_split) {
+    __shared__ __align__(16) __hip_bfloat16 As[2][PB_BM][PB_LD];
+    __shared__ __align__(16) __hip_bfloat16 Hs[2][PB_BN][PB_LD];
+    __shared__ __align__(16) __hip_bfloat16 Ls[2][PB_BN][PB_LD];
+    __shared__ double red[PB_BM][2];
     const int64_t m0 = (int64_t)blockIdx.y * PB_BM;
     const int n0 = blockIdx.x * PB_BN;
+    const int split = blockIdx.z;
+    const int kbeg = split * k_per_split;
+    const int kend = kbeg + k_per_split < Mp ? kbeg + k_per_split : Mp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    f32x16 acc = {};
-    // loader: 64 rows x 64 k bf16 = 512 chunks of 16 bytes; two per thread per matrix
-    for (int k0 = 0; k0 < Mp; k0 += PB_BK) {
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
+    // loader: each matrix tile is 128 rows x 32 k = 512 chunks of 8 bf16; two per thread
+    uint4 ra[2], rh[2], rl[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + q * 256;
-            const int r = idx >> 3;
-            const int c = (idx & 7) * 8;
+            const int r = idx >> 2;
+            const int c = (idx & 3) * 8;
             const int64_t gp = m0 + r;
-            uint4 va = make_uint4(0, 0, 0, 0);
-            if (gp < P) va = *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c);
-            *reinterpret_cast<uint4*>(&As[r][c]) = va;
-            const int64_t gn = n0 + r;
-            *reinterpret_cast<uint4*>(&Hs[r][c]) = *reinterpret_cast<const uint4*>(Vhi + gn * Mp + k0 + c);
-            *reinterpret_cast<uint4*>(&Ls[r][c]) = *reinterpret_cast<const uint4*>(Vlo + gn * Mp + k0 + c);
+            const int gn = n0 + r;
+            ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
+            rh[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vhi + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
+            rl[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vlo + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + q * 256;
+            const int r = idx >> 2;
+            const int c = (idx & 3) * 8;
+            *reinterpret_cast<uint4*>(&As[buf][r][c]) = ra[q];
+            *reinterpret_cast<uint4*>(&Hs[buf][r][c]) = rh[q];
+            *reinterpret_cast<uint4*>(&Ls[buf][r][c]) = rl[q];
+        }
+    };
+    if (kbeg < kend) {
+        fetch(kbeg);
+        stash(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += PB_BK) {
+        const bool more = k0 + PB_BK < kend;
+        if (more) fetch(k0 + PB_BK);
 #pragma unroll
         for (int ks = 0; ks < PB_BK; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
-            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Hs[wn * 32 + (lane & 31)][kk]);
-            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ls[wn * 32 + (lane & 31)][kk]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    // epilogue: lane holds D[i][j], j = lane % 32, i = 8 (v / 4) + 4 (lane / 32) + v % 4
-    const int j = lane & 31;
-    const int gn = n0 + wn * 32 + j;
-    const double htn = ht[gn];
-    double rows[16];
+            bf16x8 av[2], hv[2], lv[2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t gp = m0 + wm * 32 + i;
-        const double dqv = gp < P ? (double)__bfloat162float(dQ[gp * Mp + gn]) : 0.0;
-        rows[v] = dqv * (htn + 0.5 * (double)acc[v]);
+            for (int a = 0; a < 2; ++a)
+                av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + a * 32 + (lane & 31)][kk]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                hv[b] = *reinterpret_cast<const bf16x8*>(&Hs[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
+                lv[b] = *reinterpret_cast<const bf16x8*>(&Ls[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], hv[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], lv[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // epilogue: lane holds D[i][j] of each 32 x 32 block, j = lane % 32,
+    // i = 8 (v / 4) + 4 (lane / 32) + v % 4
+    const double first = split == 0 ? 1.0 : 0.0;
+    double rows[2][16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) rows[a][v] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int gn = n0 + wn * 64 + b * 32 + (lane & 31);
+        const bool okn = gn < M;
+        const double htn = okn ? first * ht[gn] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t gp = m0 + wm * 64 + a * 32 + i;
+                const double dqv = (okn && gp < P) ? (double)__bfloat162float(dQ[gp * Mp + gn]) : 0.0;
+                rows[a][v] += dqv * (htn + 0.5 * (double)acc[a][b][v]);
+            }
     }
     // sum over the 32 columns of the wave (lanes with equal lane / 32), fixed order
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        double x = rows[v];
-#pragma unroll
-        for (int s = 1; s < 32; s <<= 1) x += __shfl_xor(x, s, 64);
-        rows[v] = x;
-    }
-    if (j == 0) {
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            red[wm * 32 + i][wn] = rows[v];
+            double x = rows[a][v];
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) x += __shfl_xor(x, o, 64);
+            rows[a][v] = x;
         }
+    if ((lane & 31) == 0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                red[wm * 64 + a * 32 + i][wn] = rows[a][v];
+            }
     }
     __syncthreads();
     if (tid < PB_BM) {
         const int64_t gp = m0 + tid;
-        if (gp < P) part[gp * n_tiles + blockIdx.x] = red[tid][0] + red[tid][1];
+        if (gp < P) part[gp * n_tiles_total + (int64_t)blockIdx.x * gridDim.z + split] = red[tid][0] + red[tid][1];
     }
 }
 
@@ -239,20 +297,26 @@ __global__ void k_pop_finalize(int64_t P, int32_t n_tiles, const double* __restr
     E[p] = E_t + s;
 }
 
-// dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M
+// dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M; grid (Mp/512, P),
+// 8 consecutive k per thread written as one 16-byte store
 __global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
                            const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
                            const double* __restrict__ dq, __hip_bfloat16* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= P * (int64_t)Mp) return;
-    const int64_t p = idx / Mp;
-    const int k = (int)(idx - p * Mp);
-    float v = 0.0f;
-    if (k < M) {
-        const int e = occ[p * n + mob[k]];
-        v = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+    const int64_t p = blockIdx.y;
+    const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    if (k0 >= Mp) return;
+    __hip_bfloat16 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = k0 + q;
+        float x = 0.0f;
+        if (k < M) {
+            const int e = occ[p * n + mob[k]];
+            x = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+        }
+        v[q] = __float2bfloat16(x);
     }
-    out[idx] = __float2bfloat16(v);
+    *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
 }
 
 // Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
@@ -300,24 +364,30 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
-    const int32_t n_tiles = d.Mp / PB_BN;
-    const size_t dq_bytes = (size_t)P * d.Mp * sizeof(__hip_bfloat16);
-    const size_t part_bytes = (size_t)P * n_tiles * sizeof(double);
+    const int32_t n_ntiles = (d.Mp + PB_BN - 1) / PB_BN;
+    const int64_t m_tiles = (P + PB_BM - 1) / PB_BM;
+    // split K until the grid covers the compute units (the epilogue is linear in Phi)
+    int splits = 1;
+    while ((int64_t)n_ntiles * m_tiles * splits < ctx->num_cus && d.Mp / (splits * 2) >= 256 && splits < 8)
+        splits *= 2;
+    const int32_t kps = (int32_t)round_up((d.Mp + splits - 1) / splits, PB_BK);
+    const int32_t n_tiles_total = n_ntiles * splits;
+    const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
+    const size_t part_bytes = (size_t)P * n_tiles_total * sizeof(double);
     void* ws = nullptr;
-    goac_status st = workspace(ctx, 0, round_up(dq_bytes, 256) + part_bytes, &ws);
+    goac_status st = workspace(ctx, 0, dq_bytes + part_bytes, &ws);
     if (st != GOAC_OK) return st;
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
-    double* part = (double*)((char*)ws + round_up(dq_bytes, 256));
-    const int64_t tot = P * (int64_t)d.Mp;
-    hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, P, d.n, d.M,
-                       d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
+    double* part = (double*)((char*)ws + dq_bytes);
+    hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream, P,
+                       d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
     GOAC_CHECK_LAUNCH(ctx);
-    dim3 grid((unsigned)n_tiles, (unsigned)((P + PB_BM - 1) / PB_BM));
-    hipLaunchKernelGGL(k_pop_bf16, grid, dim3(256), 0, ctx->stream, P, d.Mp, dQ, d.Vhi, d.Vlo, d.ht, part,
-                       n_tiles);
+    dim3 grid((unsigned)n_ntiles, (unsigned)m_tiles, (unsigned)splits);
+    hipLaunchKernelGGL(k_pop_bf16, grid, dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo, d.ht, part,
+                       n_tiles_total, kps);
     GOAC_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, n_tiles,
-                       part, d.E_t, E);
+    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P,
+                       n_tiles_total, part, d.E_t, E);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

@@ -16,7 +16,11 @@
 // cancels in every same-sublattice swap) in FP32 and streams FP32 rows; a running
 // rigorous bound eps on |phi'32 - phi'| makes the FP32 decision final only when
 // the FP64 decision cannot differ; otherwise phi_i - phi_j is recomputed in FP64.
-// The field is re-anchored in FP64 after reanchor_every field updates.
+// The field is re-anchored in FP64 after reanchor_every field updates: inside the
+// kernel for small cells (one pass over V_mm per chain), or, for large cells, by a
+// batched FP64 matrix-core product between chunks of trials (k_anchor_* below),
+// which reads V_mm once for all due chains. The error bound stays rigorous while a
+// chain waits for its anchor; only the fallback rate grows.
 #include "common.h"
 
 namespace goac {
@@ -124,8 +128,10 @@ __device__ void anchor_chain(const McInst& I, const uint8_t* occ, const uint8_t*
     phib_out = pb;
 }
 
+// small cells run one wave per chain and want 4 resident waves per SIMD (<= 128
+// VGPRs); large cells run 4 waves per chain and are bounded by LDS
 template <bool MIXED, int WG, bool TRACE>
-__global__ __launch_bounds__(WG) void k_mc(McArgs a) {
+__global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int NW = WG / 64;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -320,19 +326,46 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                         Vj = V64 + (int64_t)bj * Mp;
                     }
                     bool over = false;
+                    // rows i and j streamed as 16-byte vectors, U vectors per thread in
+                    // flight before the field is touched
                     constexpr int VEC = MIXED ? 4 : 2;
-                    for (int k = tid * VEC; k < Mp; k += WG * VEC) {
+                    constexpr int U = WG >= 256 ? 4 : 1;   // one wave per chain: keep registers low
+                    typedef float f32x4v __attribute__((ext_vector_type(4)));
+                    typedef double f64x2v __attribute__((ext_vector_type(2)));
+                    using V16 = typename std::conditional<MIXED, f32x4v, f64x2v>::type;
+                    const GOAC_GLOBAL V16* Vi16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vi);
+                    const GOAC_GLOBAL V16* Vj16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vj);
+                    const int nv = Mp / VEC;
+                    for (int v0 = tid; v0 < nv; v0 += WG * U) {
+                        V16 a[U], b[U];
 #pragma unroll
-                        for (int q = 0; q < VEC; ++q) {
-                            T p = phi[k + q];
-                            if constexpr (MIXED) {
-                                p = fmaf(dd, Vi[k + q], p);
-                                p = fmaf(-dd, Vj[k + q], p);
-                                over |= fabsf(p) > phib;
-                            } else {
-                                p = p + dd * (Vi[k + q] - Vj[k + q]);
+                        for (int u = 0; u < U; ++u) {
+                            const int v = v0 + u * WG;
+                            if (v < nv) {
+                                a[u] = Vi16[v];
+                                b[u] = Vj16[v];
                             }
-                            phi[k + q] = p;
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int v = v0 + u * WG;
+                            if (v < nv) {
+                                const T* av = reinterpret_cast<const T*>(&a[u]);
+                                const T* bv = reinterpret_cast<const T*>(&b[u]);
+#pragma unroll
+                                for (int q = 0; q < VEC; ++q) {
+                                    const int k = v * VEC + q;
+                                    T p = phi[k];
+                                    if constexpr (MIXED) {
+                                        p = fmaf(dd, av[q], p);
+                                        p = fmaf(-dd, bv[q], p);
+                                        over |= fabsf(p) > phib;
+                                    } else {
+                                        p = p + dd * (av[q] - bv[q]);
+                                    }
+                                    phi[k] = p;
+                                }
+                            }
                         }
                     }
                     if (MIXED && over) s_flag = 1;
@@ -371,7 +404,7 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
                     const double ad = fabs(bd);
                     eps += kU32 * (2.0 * (double)phib + ad * (rmi + 2.0 * (rmi + rmj))) * 1.0001;
                     if (!(eps < 1e3)) status = 1;
-                    if (since >= (uint32_t)a.reanchor_every) {
+                    if (a.inline_anchor && since >= (uint32_t)a.reanchor_every) {
                         __syncthreads();
                         anchor_chain<WG>(I, occ, msub, chg, s_phibar, reinterpret_cast<float*>(phi), s_scr, Ecur,
                                          eps, phib);
@@ -421,6 +454,108 @@ __global__ __launch_bounds__(WG) void k_mc(McArgs a) {
             if (TRACE) sc->hash += hsum;
         }
     }
+}
+
+// ------------------------------------------------------------------ batched FP64 anchor
+// chains of one instance with since_anchor >= R: compacted list (row order is
+// immaterial: every row is computed independently) and their FP64 charges Q
+__global__ void k_anchor_select(int64_t first, int64_t C, uint32_t R, const ChainScalars* __restrict__ sc,
+                                int32_t* __restrict__ due) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    if (sc[first + c].since_anchor >= R) {
+        const int slot = atomicAdd(&due[0], 1);
+        due[1 + slot] = (int32_t)c;
+    }
+}
+
+__global__ void k_anchor_gather(int32_t M, int32_t Mp, int64_t first, const int32_t* __restrict__ due,
+                                const ChainScalars* __restrict__ sc, const uint8_t* __restrict__ occ_m,
+                                const double* __restrict__ charge, double* __restrict__ Q) {
+    const int r = blockIdx.x;
+    if (r >= due[0]) return;
+    const int64_t c = first + due[1 + r];
+    const uint8_t* o = occ_m + sc[c].off;
+    for (int k = threadIdx.x; k < Mp; k += blockDim.x) Q[(int64_t)r * Mp + k] = k < M ? charge[o[k]] : 0.0;
+}
+
+// phi' = fl32(Phi + h - phibar_s), E = E_ff + 1/2 sum q (phi + h), error bound
+__global__ __launch_bounds__(256) void k_anchor_apply(int32_t M, int32_t Mp, int64_t first,
+                                                      const int32_t* __restrict__ due, const double* __restrict__ Q,
+                                                      const double* __restrict__ Phi, const double* __restrict__ h,
+                                                      const double* __restrict__ rowabs, double qmax,
+                                                      const uint8_t* __restrict__ msub,
+                                                      const double* __restrict__ phibar, double E_ff,
+                                                      ChainScalars* __restrict__ sc, float* __restrict__ phi) {
+    __shared__ double s_a[256], s_b[256], s_c[256];
+    const int r = blockIdx.x;
+    if (r >= due[0]) return;
+    ChainScalars* S = sc + first + due[1 + r];
+    const int64_t off = S->off;
+    double es = 0.0, pm = 0.0, am = 0.0;
+    for (int k = threadIdx.x; k < M; k += 256) {
+        const double q = Q[(int64_t)r * Mp + k];
+        const double pk = Phi[(int64_t)r * Mp + k] + h[k];
+        es += q * (pk + h[k]);
+        const float v = (float)(pk - phibar[msub[k]]);
+        phi[off + k] = v;
+        pm = fmax(pm, fabs((double)v));
+        am = fmax(am, fabs(h[k]) + qmax * rowabs[k]);
+    }
+    s_a[threadIdx.x] = es;
+    s_b[threadIdx.x] = pm;
+    s_c[threadIdx.x] = am;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s_a[threadIdx.x] += s_a[threadIdx.x + w];
+            s_b[threadIdx.x] = fmax(s_b[threadIdx.x], s_b[threadIdx.x + w]);
+            s_c[threadIdx.x] = fmax(s_c[threadIdx.x], s_c[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        S->E = E_ff + 0.5 * s_a[0];
+        const double gM = (double)(M + 2) * 0x1p-53 * 1.01;
+        S->eps = kU32 * s_b[0] * 1.0001 + gM * s_c[0] * 2.0;
+        float pb = 1.0f;
+        while ((double)pb < 2.0 * s_b[0]) pb *= 2.0f;
+        S->phibound = pb;
+        S->since_anchor = 0;
+        S->anchors += 1;
+    }
+}
+
+__global__ void k_zero_one(int32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+// batched anchor of the due chains of one instance (MIXED, large cells)
+goac_status anchor_batched(goac_ctx* ctx, goac_chains* ch, int inst, uint32_t R) {
+    goac_problem* pb = ch->pbs[inst];
+    const ProblemDev& d = pb->d;
+    const int64_t Ci = ch->count[inst];
+    const int64_t first = ch->first_chain[inst];
+    if (Ci == 0) return GOAC_OK;
+    const size_t b_due = round_up((Ci + 1) * 4, 256), b_q = round_up((size_t)Ci * d.Mp * 8, 256);
+    void* ws = nullptr;
+    goac_status st = workspace(ctx, 0, b_due + 2 * b_q, &ws);
+    if (st != GOAC_OK) return st;
+    int32_t* due = (int32_t*)ws;
+    double* Q = (double*)((char*)ws + b_due);
+    double* Phi = (double*)((char*)ws + b_due + b_q);
+    hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, ctx->stream, due);
+    hipLaunchKernelGGL(k_anchor_select, dim3((unsigned)((Ci + 255) / 256)), dim3(256), 0, ctx->stream, first, Ci, R,
+                       ch->sc, due);
+    hipLaunchKernelGGL(k_anchor_gather, dim3((unsigned)Ci), dim3(256), 0, ctx->stream, d.M, d.Mp, first, due, ch->sc,
+                       ch->occ, d.charge, Q);
+    GOAC_CHECK_LAUNCH(ctx);
+    st = dgemm_nt(ctx, Ci, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, due);
+    if (st != GOAC_OK) return st;
+    hipLaunchKernelGGL(k_anchor_apply, dim3((unsigned)Ci), dim3(256), 0, ctx->stream, d.M, d.Mp, first, due, Q, Phi,
+                       d.h, d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->sc, (float*)ch->phi);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
 }
 
 // ------------------------------------------------------------------ launch
