@@ -34,6 +34,12 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit or FP64 VALU lane operations per second
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 BF16_PEAK = 2.5e15
+# HBM bytes of one k_mc<mixed, 64> launch of this step from FETCH_SIZE and WRITE_SIZE,
+# each scaled by the same counter's reading for a 256 MiB copy (factors 2.0 and 1.0);
+# valid only for the kernel sources they were taken on (profiles/k_mc_rocksalt4x4x4_traffic.md)
+MC_TRAFFIC = {"bytes": 29089401.6,
+              "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
+              "sha256": "1e34ce0adbfa7d6de9102e890521166b39d85837f3d78fe63bfdab3273bb0182"}
 
 
 def parse():
@@ -45,7 +51,20 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-FP64 and GA-energies legs")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a copy kernel of known size")
     ap.add_argument("--ga-generations", type=int, default=200)
+    ap.add_argument("--no-large", action="store_true", help="skip the 16384-site and 512-instance legs")
+    ap.add_argument("--only", default="", help="comma list of legs to run alone: fp64, ga, cfg5, cfg4 "
+                                                "(the step itself always runs unless --steps 0)")
     return ap.parse_args()
+
+
+def measured_traffic(entry):
+    """The counter-based traffic figure, or None once its kernel sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in entry["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return entry["bytes"] if h.hexdigest() == entry["sha256"] else None
 
 
 def algorithmic_ops(trials, updates, M):
@@ -141,15 +160,23 @@ def main():
         "field_updates_per_chain": upd / CHAINS,
         "fallbacks_per_chain": float(stats["fallbacks"].sum()) / CHAINS,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": measured_traffic(MC_TRAFFIC),
                      "kernel": "k_mc<mixed>", "ops_per_launch": ops},
     }
-    if not args.no_extras:
+    legs = set(args.only.split(",")) - {""}
+    if not legs and not args.no_extras:
+        legs = {"fp64", "ga"} | (set() if args.no_large else {"cfg5", "cfg4"})
+    if "fp64" in legs:
         w64, k64, s64 = timed(G.GOAC_FP64, max(2, args.steps // 2), 1)
         result["plain_fp64_trials_per_s"] = float(CHAINS) * TRIALS * max(2, args.steps // 2) / w64
         result["plain_fp64_sweep_ms"] = 1e3 * k64.mean()
         result["mixed_vs_fp64"] = result["value"] / result["plain_fp64_trials_per_s"]
+    if "ga" in legs:
         result.update(ga_energies(ctx, G, S, torch, stream, args.ga_generations))
+    if "cfg5" in legs:
+        result.update(large_cell(ctx, G, S, torch, stream))
+    if "cfg4" in legs:
+        result.update(batched_instances(ctx, G, S, torch, stream))
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -197,6 +224,83 @@ def ga_energies(ctx, G, S, torch, stream, generations):
             out["ga_mixed_mfma_frac"] = flops / (t_en / gens) / BF16_PEAK
     out["energies_per_s"] = out["ga_mixed_energies_per_s"]
     pb.close()
+    return out
+
+
+def large_cell(ctx, G, S, torch, stream):
+    """16x16x8 rock-salt (N = 16384, M = 8192): 8192 chains x 1e5 trials, kT 0.5 ->
+    0.01 eV over 100 blocks; mixed (FP32 field, batched FP64 anchors) against plain
+    FP64. The field updates stream two rows of V_mm per update: HBM roofline."""
+    cell = S.config5()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    del V
+    torch.cuda.empty_cache()
+    C, T, M = 8192, 100000, 8192
+    occ0 = pb.init_occupations(C, seed=0)
+    kT = np.geomspace(0.5, 0.01, 100)
+    out = {}
+    for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+        ch = G.Chains(pb, occ0, prec)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        ch.sweep(T, kT, T // 100, seed=0, reanchor_every=1024)
+        b.record(stream)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) * 1e-3
+        _, _, st = ch.export()
+        upd = float(st["updates"].sum())
+        row_bytes = upd * 2 * M * (4 if prec == G.GOAC_MIXED else 8)
+        out["cfg5_%s_trials_per_s" % name] = C * T / sec
+        out["cfg5_%s_sweep_s" % name] = sec
+        out["cfg5_%s_field_update_GBs" % name] = row_bytes / sec / 1e9
+        out["cfg5_%s_field_update_hbm_frac" % name] = row_bytes / sec / 1e9 / HBM_PEAK_GBS
+        if prec == G.GOAC_MIXED:
+            out["cfg5_accept_rate"] = float(st["accepts"].sum()) / (C * T)
+            out["cfg5_field_updates_per_chain"] = upd / C
+            out["cfg5_fallbacks_per_chain"] = float(st["fallbacks"].sum()) / C
+            out["cfg5_anchors_per_chain"] = float(st["anchors"].sum()) / C
+        ch.close()
+        print("  [cfg5 %s] %.3f s" % (name, sec), file=sys.stderr, flush=True)
+    out["cfg5_mixed_vs_fp64"] = out["cfg5_mixed_trials_per_s"] / out["cfg5_fp64_trials_per_s"]
+    pb.close()
+    return out
+
+
+def batched_instances(ctx, G, S, torch, stream):
+    """512 rock-salt/spinel instances (N log-uniform in [64, 2048]), 256 chains each,
+    2e4 trials, kT 0.3 -> 0.01 eV over 20 blocks, one persistent launch (mixed)."""
+    cells = S.config4()
+    t0 = time.perf_counter()
+    pbs = []
+    for c in cells:
+        V = ctx.build_ewald(c["lattice"], c["pos"])
+        pbs.append(G.Problem(ctx, V, c["sublattice"], c["species"], c["charge"]))
+    occs = [pb.init_occupations(256, seed=0, instance=i).reshape(-1) for i, pb in enumerate(pbs)]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    flat = torch.cat(occs)
+    kT = np.geomspace(0.3, 0.01, 20)
+    out = {}
+    for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+        ch = G.Chains.batch(pbs, [256] * len(pbs), flat, prec)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        ch.sweep(20000, kT, 1000, seed=0, reanchor_every=1024)
+        b.record(stream)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) * 1e-3
+        out["cfg4_%s_trials_per_s" % name] = 512 * 256 * 20000 / sec
+        out["cfg4_%s_sweep_s" % name] = sec
+        ch.close()
+        print("  [cfg4 %s] %.3f s" % (name, sec), file=sys.stderr, flush=True)
+    out["cfg4_setup_s"] = t_setup
+    for pb in pbs:
+        pb.close()
     return out
 
 

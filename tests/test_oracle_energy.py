@@ -2,6 +2,8 @@
 Coulomb Energy" and Eq. 2; "Implementation and Theoretical Background", Eq. 1;
 Results, Eq. 3)."""
 import itertools
+import json
+import os
 
 import numpy as np
 import pytest
@@ -9,18 +11,20 @@ import pytest
 import oracle as O
 import supercells as S
 
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
 
 def test_eq1_counts_match_paper():
     # Eq. 1 with vacancies counted as an element reproduces every count printed:
-    # NaCl 3x3x3 (1e64), FeSbO4 3x3x14 (1e75), LLZO 2x2x1 (1e159) and the Table 1
-    # O3 high-entropy cells (9 Na and 9 TM positions per sqrt(3) cell; Na 2/3 with
-    # vacancies; Li/Fe/Co/Ni 1/6 each, Mn 1/3).
-    assert round(O.log10_configurations([[108, 108]])) == 64
-    assert round(O.log10_configurations([[126, 126]])) == 75
-    assert round(O.log10_configurations([[192, 288], [95, 1], [29, 35]])) == 159
-    table = {(2, 2, 1): 31, (2, 2, 2): 64, (4, 4, 1): 132, (4, 4, 2): 269,
-             (6, 6, 1): 303, (8, 8, 1): 543, (6, 6, 2): 611, (6, 6, 3): 920}
-    for (a, b, c), expo in table.items():
+    # NaCl 3x3x3, FeSbO4 3x3x14, LLZO 2x2x1 and the Table 1 O3 high-entropy cells
+    # (9 Na and 9 TM positions per sqrt(3) cell; Na 2/3 with vacancies; Li/Fe/Co/Ni
+    # 1/6 each, Mn 1/3). The printed exponents are in tests/golden/paper_values.json.
+    g = GOLDEN["configuration_counts_log10"]
+    assert round(O.log10_configurations([[108, 108]])) == g["nacl_3x3x3"]
+    assert round(O.log10_configurations([[126, 126]])) == g["fesbo4_3x3x14"]
+    assert round(O.log10_configurations([[192, 288], [95, 1], [29, 35]])) == g["llzo_2x2x1"]
+    for key, expo in g["table1"].items():
+        a, b, c = (int(x) for x in key.split("x"))
         m = a * b * c
         val = O.log10_configurations([[6 * m, 3 * m], [3 * m // 2] * 4 + [3 * m]])
         assert round(val) == expo

@@ -2,6 +2,9 @@
 mathematics fix (Methodology, "Cluster Expansion of Coulomb Energy": periodic
 point-charge energies by Ewald summation; Results, "Atomistic Configurations in
 NaCl", Eq. 3 and the Madelung constant 1.74756)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -9,6 +12,7 @@ import oracle as O
 import supercells as S
 
 KE = O.coulomb_constant()
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
 
 # Madelung constants (textbook lattice sums): NaCl 1.747565 (the paper prints
 # 1.74756), CsCl 1.762675.
@@ -37,12 +41,17 @@ def test_madelung_nacl_matrix(reps, alpha):
 
 
 def test_madelung_nacl_paper_cell():
-    # the paper's 3x3x3 cell: 216 ions, r = 2.81 A, in the structure-factor form
-    lat, pos, kind = S.rocksalt_conventional(3, 3, 3, 5.62)
+    # the paper's 3x3x3 cell with its printed ion count, nearest-neighbour
+    # distance and Madelung constant (tests/golden/paper_values.json), in the
+    # structure-factor form
+    g = GOLDEN["nacl_madelung"]
+    lat, pos, kind = S.rocksalt_conventional(3, 3, 3, 2 * g["r_angstrom"])
     q = np.where(kind == 0, 1.0, -1.0)
     E = O.ewald_energy(lat, pos, q)
-    assert len(q) == 216
-    assert abs(madelung(E, 2.81, 216) - M_NACL) < 5e-7
+    assert len(q) == g["n_ions"]
+    M = madelung(E, g["r_angstrom"], g["n_ions"])
+    assert round(M, g["digits"]) == g["M"]
+    assert abs(M - M_NACL) < 5e-7
 
 
 def test_madelung_nacl_rhombohedral_cell():
