@@ -730,7 +730,7 @@ extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || k <= 0 || k > P || !occ || !idx || !Eout) return fail(ctx, GOAC_EINVAL, "topk: bad arguments");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    const size_t bE = round_up(P * 8, 256), bC = round_up(((P + 1023) / 1024) * P * 4, 256);
+    const size_t bE = round_up(P * 8, 256), bC = round_up(P * 4, 256);
     void* sel = nullptr;
     GOAC_TRY(workspace(ctx, 2, bE + bC, &sel));
     double* E = (double*)sel;
@@ -748,13 +748,17 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
     if (P > (int64_t)1 << 30) return fail(ctx, GOAC_EINVAL, "ga_generation: population too large");
     const ProblemDev& d = pb->d;
-    const size_t lds = 3 * round_up(d.M, 16);
+    // child occupation, path copy and parent B (bytes), then one bit row per species
+    // over the largest sublattice
+    int64_t max_words = 0;
+    for (int s = 0; s < d.S; ++s) max_words = std::max<int64_t>(max_words, (pb->tab_host[2 + s] + 63) / 64);
+    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * (size_t)d.E * (size_t)max_words;
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "ga_generation: too many mobile positions");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     const int32_t ne = (int32_t)std::min<int64_t>(std::max(prm->n_elite, 0), P);
     void* ws = nullptr;
     const size_t b_cum = round_up(P * 8, 256), b_el = round_up((ne + 1) * 4, 256);
-    const size_t b_cnt = round_up(((P + 1023) / 1024) * P * 4, 256);
+    const size_t b_cnt = round_up(P * 4, 256);
     GOAC_TRY(workspace(ctx, 2, b_cum + b_el + b_cnt + 256, &ws));
     uint64_t* cum = (uint64_t*)ws;
     int32_t* elite = (int32_t*)((char*)ws + b_cum);

@@ -81,16 +81,18 @@ __global__ __launch_bounds__(1024) void k_ga_prep(int64_t P, const double* __res
         cum[p] = run;
     }
     if (bad) atomicOr(err, 1);
+    // exclusive scan of the per-thread totals (Hillis-Steele, exact integers)
     s_tot[tid] = run;
     __syncthreads();
-    if (tid == 0) {
-        uint64_t acc = 0;
-        for (int q = 0; q < nt; ++q) {
-            const uint64_t v = s_tot[q];
-            s_tot[q] = acc;
-            acc += v;
-        }
+    for (int off = 1; off < nt; off <<= 1) {
+        const uint64_t v = tid >= off ? s_tot[tid - off] : 0;
+        __syncthreads();
+        s_tot[tid] += v;
+        __syncthreads();
     }
+    const uint64_t incl = s_tot[tid];
+    __syncthreads();
+    s_tot[tid] = incl - run;
     __syncthreads();
     const uint64_t base = s_tot[tid];
     for (int64_t p = lo; p < hi; ++p) cum[p] += base;
@@ -109,27 +111,60 @@ __device__ inline int64_t upper_bound_u64(const uint64_t* cum, int64_t P, uint64
     return lo;
 }
 
-// first position >= from (in the sublattice's ascending list [0, len)) whose
-// predicate holds, scanning 64 at a time with a ballot; len if none
-template <typename Pred>
-__device__ inline int wave_find(int from, int len, Pred pred) {
-    const int lane = threadIdx.x & 63;
-    for (int base = from; base < len; base += 64) {
-        const int x = base + lane;
-        const bool hit = x < len && pred(x);
-        const uint64_t m = __ballot(hit);
-        if (m) return base + (int)__ffsll((long long)m) - 1;
-    }
-    return len;
+// ------------------------------------------------------------------ GA: one child per wavefront
+constexpr int kInf = 0x7fffffff;
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// ------------------------------------------------------------------ GA: one child per wavefront
+// A wave's LDS operations complete in issue order, so ordering them across the
+// lanes of one wave needs no wait, only that the compiler keeps their order.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Position of the first set bit of a W-word bit row at word index >= w0, where
+// `win` is this lane's word w0 + lane, already loaded (and possibly modified);
+// kInf if the row has none there. Wave-uniform.
+__device__ inline int first_set(uint64_t win, int w0, int W, const uint64_t* row, int lane) {
+    uint64_t m = __ballot(win != 0);
+    while (m == 0) {
+        w0 += 64;
+        if (w0 >= W) return kInf;
+        win = w0 + lane < W ? row[w0 + lane] : 0;
+        m = __ballot(win != 0);
+    }
+    const int l = (int)__ffsll((long long)m) - 1;
+    const uint64_t v = readlane64(win, l);
+    return (w0 + l) * 64 + (int)__ffsll((long long)v) - 1;
+}
+
+// Child c of generation g (SI, "Genetic Algorithm"). Children below n_elite copy
+// the elites. Every other child draws parents A and B by roulette, crosses them
+// and may mutate:
+//   crossover: the canonical swap path from A to B is walked on a copy ref of A.
+//     Per sublattice, positions p ascending with ref[p] != B[p] take B[p] from
+//     the smallest later position q of the sublattice that holds B[p] and also
+//     disagrees with B; ref swaps p and q. The child (a second copy of A) takes
+//     each swap of the path iff the top bit of Philox(p_mobile, c, g, X) is set.
+//   mutation: with probability p_mut one valid swap, drawn as an MC proposal
+//     with the sublattice's positions ordered by (species, position).
+// The walk keeps, per species e, a bit row of the positions that still disagree
+// with B and hold e in ref, and each row's lowest set bit (lane e of hv). The
+// smallest disagreeing position p is the head of its own species' row, and q is
+// the head of B[p]'s row; a step clears p and q, sets q in the row of the species
+// q now holds unless q then agrees with B, and finds the two new heads with one
+// LDS read per row. The coin bits are drawn for 64 positions at once.
 __global__ __launch_bounds__(64) void k_ga_child(
     int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
-    const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob, const int32_t* __restrict__ fixed_idx, int32_t n_fixed,
-    const uint8_t* __restrict__ ref_occ, int64_t P, const uint8_t* __restrict__ pop_in,
-    const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite, int32_t n_elite, uint64_t seed,
-    uint32_t g, double p_mut, uint8_t* __restrict__ pop_out) {
+    const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob,
+    const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ, int64_t P,
+    const uint8_t* __restrict__ pop_in, const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite,
+    int32_t n_elite, uint64_t seed, uint32_t g, double p_mut, uint8_t* __restrict__ pop_out) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int64_t c = blockIdx.x;
     const int lane = threadIdx.x;
@@ -157,11 +192,13 @@ __global__ __launch_bounds__(64) void k_ga_child(
         pa = upper_bound_u64(cum, P, mulhi64(xa, W));
         pb = upper_bound_u64(cum, P, mulhi64(xb, W));
     }
-    // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent B)
+    // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent
+    // B); then the species bit rows of the current sublattice
     const int Mr = (int)round_up(M, 16);
     uint8_t* ch = lds;
     uint8_t* rf = lds + Mr;
     uint8_t* bb = lds + 2 * Mr;
+    uint64_t* mk = reinterpret_cast<uint64_t*>(lds + round_up(3 * (int64_t)Mr, 16));
     const uint8_t* A = pop_in + pa * n;
     const uint8_t* B = pop_in + pb * n;
     for (int x = lane; x < M; x += 64) {
@@ -171,29 +208,81 @@ __global__ __launch_bounds__(64) void k_ga_child(
         rf[x] = a;
         bb[x] = B[site];
     }
-    __syncthreads();
-    // crossover: walk the canonical swap path from A to B (positions ascending
-    // within each sublattice); each path swap enters the child with probability 1/2
+    wave_lds_order();
     for (int s = 0; s < S; ++s) {
         const int base = suboff[s], len = subsize[s];
+        const int Wd = (len + 63) >> 6;
         uint8_t* rs = rf + base;
         uint8_t* cs = ch + base;
         const uint8_t* bs = bb + base;
-        int p = 0;
-        for (;;) {
-            p = wave_find(p, len, [&](int x) { return rs[x] != bs[x]; });
-            if (p >= len) break;
-            const uint8_t want = bs[p];
-            const int q = wave_find(p + 1, len, [&](int x) { return rs[x] == want && rs[x] != bs[x]; });
-            if (q >= len) break;  // cannot happen: ref and B share the composition
-            if (lane == 0) {
-                const uint8_t t = rs[p]; rs[p] = rs[q]; rs[q] = t;
-                const u32x4 rx = philox((uint32_t)spos[base + p], (uint32_t)c, g, TAG_X, seed);
-                if (rx.x >> 31) { const uint8_t t2 = cs[p]; cs[p] = cs[q]; cs[q] = t2; }
+        // bit rows: mk[e * Wd + w] bit l <=> position 64 w + l holds e and disagrees with B
+        for (int w = 0; w < Wd; ++w) {
+            const int x = w * 64 + lane;
+            const int rv = x < len ? rs[x] : 255;
+            const bool mis = x < len && rv != bs[x];
+            for (int e = 0; e < E; ++e) {
+                const uint64_t m = __ballot(mis && rv == e);
+                if (lane == 0) mk[e * Wd + w] = m;
             }
-            __syncthreads();
-            ++p;
         }
+        wave_lds_order();
+        int hv = kInf;   // lane e: head of species e's row
+        for (int e = 0; e < E; ++e) {
+            const uint64_t v = lane < Wd ? mk[e * Wd + lane] : 0;
+            const int h = first_set(v, 0, Wd, mk + e * Wd, lane);
+            if (lane == e) hv = h;
+        }
+        bool bad = false;
+        for (int w = 0; w < Wd && !bad; ++w) {
+            const int x = w * 64 + lane;
+            const bool in = x < len;
+            int rv = in ? rs[x] : 0;
+            const int bv = in ? bs[x] : 0;
+            uint64_t mm = __ballot(in && rv != bv);
+            if (!mm) continue;
+            bool coin = false;
+            if (in) coin = (philox((uint32_t)spos[base + x], (uint32_t)c, g, TAG_X, seed).x >> 31) != 0;
+            const uint64_t xm = __ballot(coin);
+            while (mm) {
+                const int po = (int)__ffsll((long long)mm) - 1;
+                mm &= mm - 1;
+                const int p = w * 64 + po;
+                const int a = __builtin_amdgcn_readlane(rv, po);
+                const int b = __builtin_amdgcn_readlane(bv, po);
+                if (a >= E || b >= E) { bad = true; break; }         // species id out of range
+                const int q = __builtin_amdgcn_readlane(hv, b);
+                if (q >= len) { bad = true; break; }                 // broken composition
+                const int qw = q >> 6, dq = qw - w;
+                uint64_t* rowb = mk + b * Wd;
+                uint64_t* rowa = mk + a * Wd;
+                uint64_t wb = qw + lane < Wd ? rowb[qw + lane] : 0;
+                uint64_t wa = w + lane < Wd ? rowa[w + lane] : 0;
+                const bool carry = bs[q] != a;   // q keeps disagreeing with B after taking a
+                const uint64_t bitq = 1ull << (q & 63), bitp = 1ull << po;
+                if (lane == 0) { wb &= ~bitq; wa &= ~bitp; }
+                if (carry && dq < 64 && lane == dq) wa |= bitq;
+                if (lane == 0) { rowb[qw] = wb; rowa[w] = wa; }
+                if (carry && dq > 0 && dq < 64 && lane == dq) rowa[qw] = wa;
+                if (carry && dq >= 64 && lane == 0) rowa[qw] |= bitq;
+                if (lane == 0) rs[q] = (uint8_t)a;
+                if (((xm >> po) & 1) && lane == 0) {
+                    const uint8_t t = cs[p];
+                    cs[p] = cs[q];
+                    cs[q] = t;
+                }
+                wave_lds_order();
+                const int hb = first_set(wb, qw, Wd, rowb, lane);
+                int ha = first_set(wa, w, Wd, rowa, lane);
+                if (carry && dq >= 64) ha = min(ha, q);
+                hv = lane == b ? hb : hv;
+                hv = lane == a ? ha : hv;
+                if (dq == 0) {
+                    if (lane == (q & 63)) rv = a;
+                    if (!carry) mm &= ~bitq;
+                }
+            }
+        }
+        wave_lds_order();
     }
     // mutation: one valid swap with probability p_mut
     const u32x4 rm = philox((uint32_t)c, g, 1u, TAG_MUT, seed);
@@ -203,9 +292,9 @@ __global__ __launch_bounds__(64) void k_ga_child(
         const int base = suboff[s];
         const int px = spos_inv[im] - base;
         const uint8_t a = ch[base + px];
-        const int na = cnt[s * E + a];
+        const int na = a < E ? cnt[s * E + a] : 0;
         const int cn = subsize[s] - na;
-        if (cn > 0) {
+        if (a < E && cn > 0) {
             const int k = (int)mulshift(rm.y, (uint32_t)cn);
             const int idx = k < offs[s * E + a] ? k : k + na;
             int e = 0;
@@ -230,7 +319,7 @@ __global__ __launch_bounds__(64) void k_ga_child(
             if (lane == 0 && pos >= 0) {
                 const uint8_t t = ch[base + px]; ch[base + px] = ch[base + pos]; ch[base + pos] = t;
             }
-            __syncthreads();
+            wave_lds_order();
         }
     }
     for (int x = lane; x < M; x += 64) out[mob[spos[x]]] = ch[x];
@@ -239,38 +328,37 @@ __global__ __launch_bounds__(64) void k_ga_child(
 
 // ------------------------------------------------------------------ ranking
 // rank(p) = #{q : (E_q, q) < (E_p, p)} (a strict total order, so ranks are
-// distinct); the k smallest ranks are the k lowest configurations. Partial
-// counts over segments of q run in parallel (one thread per (p, segment), the
-// segment staged in LDS), then are summed in segment order.
-constexpr int RK_SEG = 1024;
+// distinct); the k smallest ranks are the k lowest configurations. A workgroup
+// counts, for its 256 p, the q of one 64-wide segment staged in LDS and adds the
+// count to rank(p) with an integer atomic (exact, so the order of the additions
+// does not matter).
+constexpr int RK_SEG = 64;
 
-__global__ __launch_bounds__(256) void k_rank_partial(int64_t P, const double* __restrict__ E,
-                                                      int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void k_rank_count(int64_t P, const double* __restrict__ E,
+                                                    int32_t* __restrict__ cnt) {
     __shared__ double tile[RK_SEG];
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t seg = blockIdx.y;
-    const int64_t b0 = seg * RK_SEG;
-    const int len = (int)(P - b0 < RK_SEG ? P - b0 : RK_SEG);
-    for (int x = threadIdx.x; x < len; x += 256) tile[x] = E[b0 + x];
-    __syncthreads();
-    if (p >= P) return;
-    const double ep = E[p];
+    const double ep = p < P ? E[p] : 0.0;
     int c = 0;
-    for (int x = 0; x < len; ++x) {
-        const double eq = tile[x];
-        c += (eq < ep || (eq == ep && b0 + x < p)) ? 1 : 0;
+    for (int64_t b0 = (int64_t)blockIdx.y * RK_SEG; b0 < P; b0 += (int64_t)gridDim.y * RK_SEG) {
+        const int len = (int)(P - b0 < RK_SEG ? P - b0 : RK_SEG);
+        __syncthreads();
+        if (threadIdx.x < len) tile[threadIdx.x] = E[b0 + threadIdx.x];
+        __syncthreads();
+        for (int x = 0; x < len; ++x) {
+            const double eq = tile[x];
+            c += (eq < ep || (eq == ep && b0 + x < p)) ? 1 : 0;
+        }
     }
-    cnt[seg * P + p] = c;
+    if (p < P && c) atomicAdd(cnt + p, c);
 }
 
 // idx[rank] = p (int64 or int32 output) and Eout[rank] = E_p for rank < k
-__global__ void k_rank_finish(int64_t P, int32_t n_seg, int32_t k, const double* __restrict__ E,
-                              const int32_t* __restrict__ cnt, int64_t* __restrict__ idx64,
-                              int32_t* __restrict__ idx32, double* __restrict__ Eout) {
+__global__ void k_rank_finish(int64_t P, int32_t k, const double* __restrict__ E, const int32_t* __restrict__ cnt,
+                              int64_t* __restrict__ idx64, int32_t* __restrict__ idx32, double* __restrict__ Eout) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    int64_t r = 0;
-    for (int s = 0; s < n_seg; ++s) r += cnt[(int64_t)s * P + p];
+    const int64_t r = cnt[p];
     if (r < k) {
         if (idx64) idx64[r] = p;
         if (idx32) idx32[r] = (int32_t)p;
@@ -278,14 +366,20 @@ __global__ void k_rank_finish(int64_t P, int32_t n_seg, int32_t k, const double*
     }
 }
 
+__global__ void k_zero_rank(int64_t P, int32_t* __restrict__ cnt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) cnt[p] = 0;
+}
+
+// cnt_scratch: P int32
 goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, int32_t* cnt_scratch,
                         int64_t* idx64, int32_t* idx32, double* Eout) {
     if (k <= 0 || P <= 0) return GOAC_OK;
-    const int32_t n_seg = (int32_t)((P + RK_SEG - 1) / RK_SEG);
-    dim3 g1((unsigned)((P + 255) / 256), (unsigned)n_seg);
-    hipLaunchKernelGGL(k_rank_partial, g1, dim3(256), 0, ctx->stream, P, E, cnt_scratch);
-    hipLaunchKernelGGL(k_rank_finish, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P, n_seg, k, E,
-                       cnt_scratch, idx64, idx32, Eout);
+    const unsigned pb = (unsigned)((P + 255) / 256);
+    hipLaunchKernelGGL(k_zero_rank, dim3(pb), dim3(256), 0, ctx->stream, P, cnt_scratch);
+    dim3 g1(pb, (unsigned)std::min<int64_t>((P + RK_SEG - 1) / RK_SEG, 65535));
+    hipLaunchKernelGGL(k_rank_count, g1, dim3(256), 0, ctx->stream, P, E, cnt_scratch);
+    hipLaunchKernelGGL(k_rank_finish, dim3(pb), dim3(256), 0, ctx->stream, P, k, E, cnt_scratch, idx64, idx32, Eout);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

@@ -214,13 +214,18 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         uint64_t bnd = (blk0 + 1) * a.block_len;
         const bool wide_blocks = a.block_len >= (uint64_t)WG;
         const uint64_t nb1 = (uint64_t)(a.n_blocks - 1);
+        double kT0 = 0.0, kT1 = 0.0;   // temperatures of blocks blk0 and blk0 + 1
+        uint64_t kblk = ~(uint64_t)0;
         while (t < t_end) {
             const uint64_t tl = t + (uint64_t)tid;
             const bool valid = tl < t_end;
             double kT;
             if (wide_blocks) {
-                const double kT0 = kTrow[blk0 < nb1 ? blk0 : nb1];
-                const double kT1 = kTrow[blk0 + 1 < nb1 ? blk0 + 1 : nb1];
+                if (blk0 != kblk) {
+                    kT0 = kTrow[blk0 < nb1 ? blk0 : nb1];
+                    kT1 = kTrow[blk0 + 1 < nb1 ? blk0 + 1 : nb1];
+                    kblk = blk0;
+                }
                 kT = tl >= bnd ? kT1 : kT0;
             } else {
                 const uint64_t blk = tl / a.block_len;
@@ -246,14 +251,19 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 const double Vij = V64[(int64_t)i * Mp + j];
                 dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
                 // Metropolis threshold L = -kT ln u, first in FP32 from the top 24 bits
-                // of u: |L32 - L| <= m32 (u32 within 2^-25 of u, log within 2^-20 relative);
-                // tests closer than m32 to the threshold use the exact FP64 rule
+                // of u: |L32 - L| <= m32. u32 lies within 2^-25 of u, so its logarithm
+                // is off by at most 0.625 2^-24 / u32 (ub >= 2); the hardware log2
+                // (1 ulp), the product with ln 2 and with kT add at most 2^-21 relative,
+                // half the band's 2^-20. Tests closer than m32 to the threshold use the
+                // exact FP64 rule.
                 const uint32_t ub = r.z >> 8;
                 const float u32 = ((float)ub + 0.5f) * 0x1p-24f;
-                const float lg = __logf(u32);
+                const float lg = __builtin_amdgcn_logf(u32) * 0.693147182f;
                 const float kTf = (float)kT;
                 const double L32 = (double)(-kTf * lg);
-                const double m32 = ub < 2 ? INFINITY : (double)(kTf * (0x1p-24f / u32 + 0x1p-20f * (1.0f - lg)));
+                const double m32 = ub < 2 ? INFINITY
+                                          : (double)(kTf * (0x1p-24f * __builtin_amdgcn_rcpf(u32) +
+                                                            0x1p-20f * (1.0f - lg)));
                 if constexpr (MIXED) {
                     const double e = d != 0.0 ? 2.0 * fabs(d) * eps + kMargin : 0.0;
                     const double hi = dE + e, lo = dE - e;
