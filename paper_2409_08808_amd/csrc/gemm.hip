@@ -5,6 +5,8 @@
 //   k_pop_bf16      Phi = dQ (V_hi + V_lo) with bf16 inputs and FP32 accumulation
 //                   (v_mfma_f32_32x32x16_bf16) and a fused FP64 row-dot epilogue:
 //                   the mixed-precision population energies.
+#include <algorithm>
+
 #include "common.h"
 
 namespace goac {
@@ -148,61 +150,101 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 // ------------------------------------------------------------------ bf16 hi+lo population GEMM
 // Phi[p][n] = sum_k dQ[p][k] (Vhi[n][k] + Vlo[n][k]) (V is symmetric, so its rows
 // serve as columns), bf16 inputs, FP32 accumulation on v_mfma_f32_32x32x16_bf16.
-// Fused epilogue per output tile, in FP64 (linear in Phi, so K may be split):
-//   part[p][t] = sum_{n in tile} dQ[p][n] (ht[n] [first K slice only] + Phi_slice[p][n] / 2)
-// Tile 128 (p) x 128 (n) x 32 (k), 256 threads = 2 x 2 waves, each wave 64 x 64 =
-// 2 x 2 accumulators, each fed by the hi and the lo operand: 8 MFMAs per 6 LDS
-// operand reads. The next K stage is fetched into registers while the matrix
-// cores work on the current one; double-buffered LDS, one barrier per stage.
-constexpr int PB_BM = 128, PB_BN = 128, PB_BK = 32, PB_LD = PB_BK + 8;
+// Fused epilogue per output tile (linear in Phi, so K may be split):
+//   part[t][p] = 1/2 sum_{n in tile} dQ[p][n] Phi_slice[p][n]
+// in FP32 within the tile (dQ is a small integer; the error stays orders of
+// magnitude below the FP32 accumulation of Phi itself) and FP64 across tiles. The
+// linear term dQ . ht is added in FP64 by k_pop_finalize.
+// Tile 256 (p) x 128 (n) x 32 (k), 256 threads = 2 x 2 waves, each wave 128 x 64 =
+// 4 x 2 accumulators, each fed by the hi and the lo operand: 16 MFMAs per 8 LDS
+// operand reads (the hi/lo pair doubles the n-side operand, so the wave tile is
+// long in p). The next K stage is fetched into registers while the matrix cores
+// work on the current one; double-buffered LDS (80 KiB, two workgroups per
+// compute unit), one barrier per stage.
+//
+// Workgroup order. Each XCD has its own L2, and workgroups are dealt to the XCDs
+// round-robin. Order 0 decodes the linear id as (n-tile, p-tile, K-slice) with
+// the K-slice fastest, so the K-slices of a tile land on different XCDs and an
+// XCD streams one K range of every operand; order 1 first gives each XCD a
+// contiguous block of linear ids, so it streams a few column tiles over all K.
+// The host picks the order with the smaller largest per-XCD working set.
+constexpr int PB_BM = 256, PB_BN = 128, PB_BK = 32, PB_LD = PB_BK + 8, PB_DLD = PB_BN + 8;
+constexpr int kPopLds = 2 * (PB_BM + 2 * PB_BN) * PB_LD * 2;   // 80 KiB
+static_assert(PB_BM * PB_DLD * 2 + PB_BM * 2 * 8 <= kPopLds, "epilogue staging exceeds the stage buffers");
+constexpr int kXcds = 8;
 
-__global__ __launch_bounds__(256) void k_pop_bf16(int64_t P, int32_t M, int32_t Mp,
-                                                  const __hip_bfloat16* __restrict__ dQ,
-                                                  const __hip_bfloat16* __restrict__ Vhi,
-                                                  const __hip_bfloat16* __restrict__ Vlo,
-                                                  const double* __restrict__ ht, double* __restrict__ part,
-                                                  int32_t n_tiles_total, int32_t k_per_split) {
-    __shared__ __align__(16) __hip_bfloat16 As[2][PB_BM][PB_LD];
-    __shared__ __align__(16) __hip_bfloat16 Hs[2][PB_BN][PB_LD];
-    __shared__ __align__(16) __hip_bfloat16 Ls[2][PB_BN][PB_LD];
-    __shared__ double red[PB_BM][2];
-    const int64_t m0 = (int64_t)blockIdx.y * PB_BM;
-    const int n0 = blockIdx.x * PB_BN;
-    const int split = blockIdx.z;
+__device__ __forceinline__ void pop_tile_of(int order, int id, int MT, int S, int total, int& mt, int& nt,
+                                            int& split) {
+    int u = id;
+    if (order == 1) u = (id % kXcds) * (total / kXcds) + id / kXcds;
+    nt = u / (MT * S);
+    const int rem = u - nt * (MT * S);
+    mt = rem / S;
+    split = rem - mt * S;
+}
+
+__global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32_t Mp,
+                                                     const __hip_bfloat16* __restrict__ dQ,
+                                                     const __hip_bfloat16* __restrict__ Vhi,
+                                                     const __hip_bfloat16* __restrict__ Vlo,
+                                                     double* __restrict__ part, int32_t MT, int32_t S,
+                                                     int32_t k_per_split, int32_t order) {
+    // operand stages during the K loop; the epilogue reuses the same bytes for the
+    // tile's dQ block and the row sums
+    __shared__ __align__(16) unsigned char smem[kPopLds];
+    auto As = reinterpret_cast<__hip_bfloat16 (*)[PB_BM][PB_LD]>(smem);
+    auto Hs = reinterpret_cast<__hip_bfloat16 (*)[PB_BN][PB_LD]>(smem + 2 * PB_BM * PB_LD * 2);
+    auto Ls = reinterpret_cast<__hip_bfloat16 (*)[PB_BN][PB_LD]>(smem + 2 * (PB_BM + PB_BN) * PB_LD * 2);
+    auto Ds = reinterpret_cast<__hip_bfloat16 (*)[PB_DLD]>(smem);
+    auto red = reinterpret_cast<double (*)[2]>(smem + PB_BM * PB_DLD * 2);
+    const int total = (int)gridDim.x;
+    int mt, nt, split;
+    pop_tile_of(order, (int)blockIdx.x, MT, S, total, mt, nt, split);
+    const int64_t m0 = (int64_t)mt * PB_BM;
+    const int n0 = nt * PB_BN;
     const int kbeg = split * k_per_split;
     const int kend = kbeg + k_per_split < Mp ? kbeg + k_per_split : Mp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    f32x16 acc[2][2];
+    f32x16 acc[4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
-    // loader: each matrix tile is 128 rows x 32 k = 512 chunks of 8 bf16; two per thread
-    uint4 ra[2], rh[2], rl[2];
+    // loader: the p-tile is 256 rows x 32 k = 1024 chunks of 8 bf16 (four per
+    // thread), each n-tile 128 rows x 32 k (two per thread)
+    uint4 ra[4], rh[2], rl[2];
     auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256;
+            const int r = idx >> 2;
+            const int c = (idx & 3) * 8;
+            const int64_t gp = m0 + r;
+            ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + q * 256;
             const int r = idx >> 2;
             const int c = (idx & 3) * 8;
-            const int64_t gp = m0 + r;
             const int gn = n0 + r;
-            ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
             rh[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vhi + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
             rl[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vlo + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256;
+            *reinterpret_cast<uint4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
+        }
+#pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + q * 256;
-            const int r = idx >> 2;
-            const int c = (idx & 3) * 8;
-            *reinterpret_cast<uint4*>(&As[buf][r][c]) = ra[q];
-            *reinterpret_cast<uint4*>(&Hs[buf][r][c]) = rh[q];
-            *reinterpret_cast<uint4*>(&Ls[buf][r][c]) = rl[q];
+            *reinterpret_cast<uint4*>(&Hs[buf][idx >> 2][(idx & 3) * 8]) = rh[q];
+            *reinterpret_cast<uint4*>(&Ls[buf][idx >> 2][(idx & 3) * 8]) = rl[q];
         }
     };
     if (kbeg < kend) {
@@ -217,84 +259,99 @@ __global__ __launch_bounds__(256) void k_pop_bf16(int64_t P, int32_t M, int32_t 
 #pragma unroll
         for (int ks = 0; ks < PB_BK; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
-            bf16x8 av[2], hv[2], lv[2];
+            bf16x8 av[4], hv[2], lv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + a * 32 + (lane & 31)][kk]);
+            for (int a = 0; a < 4; ++a)
+                av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 128 + a * 32 + (lane & 31)][kk]);
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 hv[b] = *reinterpret_cast<const bf16x8*>(&Hs[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
                 lv[b] = *reinterpret_cast<const bf16x8*>(&Ls[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], hv[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], lv[b], acc[a][b], 0, 0, 0);
-                }
         }
         if (more) stash(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
-    // epilogue: lane holds D[i][j] of each 32 x 32 block, j = lane % 32,
-    // i = 8 (v / 4) + 4 (lane / 32) + v % 4
-    const double first = split == 0 ? 1.0 : 0.0;
-    double rows[2][16];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) rows[a][v] = 0.0;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int gn = n0 + wn * 64 + b * 32 + (lane & 31);
-        const bool okn = gn < M;
-        const double htn = okn ? first * ht[gn] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int64_t gp = m0 + wm * 64 + a * 32 + i;
-                const double dqv = (okn && gp < P) ? (double)__bfloat162float(dQ[gp * Mp + gn]) : 0.0;
-                rows[a][v] += dqv * (htn + 0.5 * (double)acc[a][b][v]);
-            }
-    }
-    // sum over the 32 columns of the wave (lanes with equal lane / 32), fixed order
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            double x = rows[a][v];
-#pragma unroll
-            for (int o = 1; o < 32; o <<= 1) x += __shfl_xor(x, o, 64);
-            rows[a][v] = x;
-        }
-    if ((lane & 31) == 0) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                red[wm * 64 + a * 32 + i][wn] = rows[a][v];
-            }
+    // epilogue. The tile's dQ block (256 p x 128 n) is staged in LDS with 16-byte
+    // loads. Lane holds D[i][j] of each 32 x 32 block, j = lane % 32,
+    // i = 8 (v / 4) + 4 (lane / 32) + v % 4; per 32-row block the lane forms
+    // x_v = sum_b dQ[i][j_b] D_b[i][j] and a halving butterfly over the 32 lanes of
+    // its half (masks 16, 8, 4, 2, 1, each step keeping half of the rows) leaves
+    // row v(lane) summed over all 32 columns in lanes 2c and 2c + 1 (fixed order,
+    // deterministic).
+    for (int x = tid; x < PB_BM * (PB_BN / 8); x += 256) {
+        const int r = x / (PB_BN / 8), c = (x % (PB_BN / 8)) * 8;
+        const int64_t gp = m0 + r;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gp < P && n0 + c < Mp) v = *reinterpret_cast<const uint4*>(dQ + gp * Mp + n0 + c);
+        *reinterpret_cast<uint4*>(&Ds[r][c]) = v;
     }
     __syncthreads();
-    if (tid < PB_BM) {
-        const int64_t gp = m0 + tid;
-        if (gp < P) part[gp * n_tiles_total + (int64_t)blockIdx.x * gridDim.z + split] = red[tid][0] + red[tid][1];
+    const int c32 = lane & 31, h = lane >> 5;
+    const int vkeep = ((c32 >> 4) & 1) * 8 + ((c32 >> 3) & 1) * 4 + ((c32 >> 2) & 1) * 2 + ((c32 >> 1) & 1);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        float x[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * h + (v & 3);
+            const int r = wm * 128 + a * 32 + i;
+            float s2 = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) s2 += __bfloat162float(Ds[r][wn * 64 + b * 32 + c32]) * acc[a][b][v];
+            x[v] = s2;
+        }
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1) {
+            const bool low = (c32 & (2 * w)) == 0;   // keep rows v < w of the current block
+#pragma unroll
+            for (int v = 0; v < w; ++v) {
+                const float send = low ? x[v + w] : x[v];
+                const float recv = __shfl_xor(send, 2 * w, 64);
+                x[v] = (low ? x[v] : x[v + w]) + recv;
+            }
+        }
+        const float tot = x[0] + __shfl_xor(x[0], 1, 64);
+        if ((c32 & 1) == 0) {
+            const int i = 8 * (vkeep >> 2) + 4 * h + (vkeep & 3);
+            red[wm * 128 + a * 32 + i][wn] = (double)tot;
+        }
     }
+    __syncthreads();
+    const int64_t gp = m0 + tid;
+    if (gp < P) part[(int64_t)(nt * S + split) * P + gp] = 0.5 * (red[tid][0] + red[tid][1]);
 }
 
-// E[p] = E~ + sum over column tiles of part[p][t], in tile order
-__global__ void k_pop_finalize(int64_t P, int32_t n_tiles, const double* __restrict__ part, double E_t,
-                               double* __restrict__ E) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// E[p] = E~ + lin[p] + sum over (column tile, K slice) t of part[t][p], with
+// lin[p] = sum_k dQ[p][k] ht[k] (FP64) from the row builder or, when it did not
+// form it, here: one wavefront per row, each lane sums its strided share in
+// order, then a fixed butterfly
+__global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int32_t Mp, int32_t n_tiles,
+                                                      const __hip_bfloat16* __restrict__ dQ,
+                                                      const double* __restrict__ ht, const double* __restrict__ part,
+                                                      const double* __restrict__ lin, double E_t,
+                                                      double* __restrict__ E) {
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (p >= P) return;
     double s = 0.0;
-    for (int t = 0; t < n_tiles; ++t) s += part[p * n_tiles + t];
-    E[p] = E_t + s;
+    if (!lin)
+        for (int k = lane; k < M; k += 64) s += (double)__bfloat162float(dQ[p * Mp + k]) * ht[k];
+    for (int t = lane; t < n_tiles; t += 64) s += part[(int64_t)t * P + p];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) E[p] = E_t + (lin ? lin[p] + s : s);
 }
 
 // dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M; grid (Mp/512, P),
@@ -317,6 +374,58 @@ __global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t 
         v[q] = __float2bfloat16(x);
     }
     *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
+}
+
+// The same for rows of at most kDqStageMax sites: one workgroup per row reads the
+// row into LDS with coalesced 16-byte loads, then gathers from LDS. It also forms
+// the row's linear term lin[p] = sum_k dQ[p][k] ht[k] in FP64 (each thread sums its
+// k in order, then a fixed butterfly and the four waves in order).
+constexpr int64_t kDqStageMax = 48 * 1024;
+
+__global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E,
+                                                         const uint8_t* __restrict__ occ,
+                                                         const int32_t* __restrict__ mob,
+                                                         const uint8_t* __restrict__ msub,
+                                                         const double* __restrict__ dq,
+                                                         const double* __restrict__ ht,
+                                                         __hip_bfloat16* __restrict__ out,
+                                                         double* __restrict__ lin) {
+    extern __shared__ __align__(16) uint8_t row[];
+    __shared__ double wsum[4];
+    const int64_t p = blockIdx.x;
+    const uint8_t* src = occ + p * n;
+    // rows start at p * n bytes: 16-byte loads only when that is aligned
+    if ((((uintptr_t)src) & 15) == 0) {
+        for (int64_t x = threadIdx.x * 16; x < n; x += 256 * 16) {
+            if (x + 16 <= n) *reinterpret_cast<uint4*>(row + x) = *reinterpret_cast<const uint4*>(src + x);
+            else
+                for (int64_t y = x; y < n; ++y) row[y] = src[y];
+        }
+    } else {
+        for (int64_t x = threadIdx.x; x < n; x += 256) row[x] = src[x];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int k0 = threadIdx.x * 8; k0 < Mp; k0 += 256 * 8) {
+        __hip_bfloat16 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = k0 + q;
+            double x = 0.0;
+            if (k < M) {
+                const int e = row[mob[k]];
+                x = dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+                acc += x * ht[k];
+            }
+            v[q] = __float2bfloat16((float)x);
+        }
+        *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) lin[p] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
 // Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
@@ -361,33 +470,66 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
     return GOAC_OK;
 }
 
+// Largest number of distinct operand bytes one XCD streams under a workgroup order
+// (the p-rows and n-rows of every K slice its workgroups touch).
+static double pop_xcd_bytes(int order, int MT, int NT, int S, int kps) {
+    const int total = MT * NT * S;
+    double worst = 0.0;
+    for (int x = 0; x < kXcds; ++x) {
+        std::vector<char> a((size_t)MT * S, 0), b((size_t)NT * S, 0);
+        for (int id = x; id < total; id += kXcds) {
+            int u = id;
+            if (order == 1) u = (id % kXcds) * (total / kXcds) + id / kXcds;
+            const int nt = u / (MT * S), rem = u - nt * (MT * S), mt = rem / S, sp = rem - mt * S;
+            a[(size_t)mt * S + sp] = 1;
+            b[(size_t)nt * S + sp] = 1;
+        }
+        double bytes = 0.0;
+        for (char c : a) bytes += c ? (double)PB_BM * kps * 2 : 0.0;
+        for (char c : b) bytes += c ? (double)PB_BN * kps * 4 : 0.0;
+        worst = std::max(worst, bytes);
+    }
+    return worst;
+}
+
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
-    const int32_t n_ntiles = (d.Mp + PB_BN - 1) / PB_BN;
-    const int64_t m_tiles = (P + PB_BM - 1) / PB_BM;
-    // split K until the grid covers the compute units (the epilogue is linear in Phi)
-    int splits = 1;
-    while ((int64_t)n_ntiles * m_tiles * splits < ctx->num_cus && d.Mp / (splits * 2) >= 256 && splits < 8)
-        splits *= 2;
-    const int32_t kps = (int32_t)round_up((d.Mp + splits - 1) / splits, PB_BK);
-    const int32_t n_tiles_total = n_ntiles * splits;
+    const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
+    const int64_t MT = (P + PB_BM - 1) / PB_BM;
+    if (MT * NT > (int64_t)1 << 24) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
+    // split K until the grid holds two workgroups per compute unit (the epilogue is
+    // linear in Phi), so that one workgroup's loads overlap the other's matrix work
+    int S = 1;
+    while (MT * NT * S < 2 * (int64_t)ctx->num_cus && d.Mp / (S * 2) >= 256 && S < 16) S *= 2;
+    const int32_t kps = (int32_t)round_up((d.Mp + S - 1) / S, PB_BK);
+    const int64_t total = MT * NT * S;
+    int order = 0;
+    if (total % kXcds == 0 && total <= (1 << 16) &&
+        pop_xcd_bytes(1, (int)MT, NT, S, kps) < pop_xcd_bytes(0, (int)MT, NT, S, kps))
+        order = 1;
+    const int32_t n_parts = NT * S;
     const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
-    const size_t part_bytes = (size_t)P * n_tiles_total * sizeof(double);
+    const size_t part_bytes = round_up((size_t)P * n_parts * sizeof(double), 256);
     void* ws = nullptr;
-    goac_status st = workspace(ctx, 0, dq_bytes + part_bytes, &ws);
+    goac_status st = workspace(ctx, 0, dq_bytes + part_bytes + (size_t)P * sizeof(double), &ws);
     if (st != GOAC_OK) return st;
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
     double* part = (double*)((char*)ws + dq_bytes);
-    hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream, P,
-                       d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
+    double* lin = nullptr;
+    if (d.n <= kDqStageMax) {
+        lin = (double*)((char*)ws + dq_bytes + part_bytes);
+        hipLaunchKernelGGL(k_build_dq_staged, dim3((unsigned)P), dim3(256), round_up(d.n, 16), ctx->stream, P, d.n,
+                           d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+    } else
+        hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream,
+                           P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
     GOAC_CHECK_LAUNCH(ctx);
-    dim3 grid((unsigned)n_ntiles, (unsigned)m_tiles, (unsigned)splits);
-    hipLaunchKernelGGL(k_pop_bf16, grid, dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo, d.ht, part,
-                       n_tiles_total, kps);
+    hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)total), dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo,
+                       part, (int32_t)MT, S, kps, order);
     GOAC_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P,
-                       n_tiles_total, part, d.E_t, E);
+    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
+                       n_parts, dQ, d.ht, part, lin, d.E_t, E);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
