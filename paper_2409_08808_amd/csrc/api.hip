@@ -752,7 +752,8 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
     // over the largest sublattice
     int64_t max_words = 0;
     for (int s = 0; s < d.S; ++s) max_words = std::max<int64_t>(max_words, (pb->tab_host[2 + s] + 63) / 64);
-    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * (size_t)d.E * (size_t)max_words;
+    // (at least 16 x 64 words: the register-resident walk builds its rows there)
+    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * std::max<size_t>((size_t)d.E * (size_t)max_words, 16 * 64);
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "ga_generation: too many mobile positions");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     const int32_t ne = (int32_t)std::min<int64_t>(std::max(prm->n_elite, 0), P);

@@ -143,6 +143,158 @@ __device__ inline int first_set(uint64_t win, int w0, int W, const uint64_t* row
     return (w0 + l) * 64 + (int)__ffsll((long long)v) - 1;
 }
 
+// Crossover walk of one sublattice held in registers (len <= 4096 positions,
+// species ids < kRegSpecies). Lane l owns positions 64 l .. 64 l + 63: the bytes of
+// ref (the path copy), of parent B and of the child in R, Bv, Cv (dword d holds
+// positions 4 d .. 4 d + 3), one 64-bit word of each species' bit row (bit j: the
+// position holds e in ref and disagrees with B), the word of disagreeing positions
+// still to visit (mm), and, in lane e, the head of species e's row. A step reads
+// and writes single bytes and words of given lanes with uniform register indices
+// (no memory traffic); the coin bits of a chunk are drawn when the walk enters
+// it. Returns false on a species id out of range or a broken composition.
+constexpr int kRegSpecies = 16;
+constexpr int kRegMaxLen = 64 * 64;
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
+
+__device__ bool crossover_regs(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s,
+                               uint64_t* mk, uint32_t c, uint32_t g, uint64_t seed, int lane) {
+    uint32_t R[16], Bv[16], Cv[16];
+    const int x0 = lane * 64;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        uint32_t r = 0, b = 0, ch = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * d + k;
+            if (x < len) {
+                r |= (uint32_t)rs[x] << (8 * k);
+                b |= (uint32_t)bs[x] << (8 * k);
+                ch |= (uint32_t)cs[x] << (8 * k);
+            }
+        }
+        R[d] = r;
+        Bv[d] = b;
+        Cv[d] = ch;
+    }
+    // species rows through LDS: lane l ors bit j into mk[e][l] for each of its
+    // disagreeing positions (each lane touches only its own column)
+    for (int e = 0; e < kRegSpecies; ++e) mk[e * 64 + lane] = 0;
+    wave_lds_order();
+    uint64_t mm = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 16; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t e = byte_of(R[d], k), b = byte_of(Bv[d], k);
+            if (e != b) {
+                if (e < kRegSpecies && b < kRegSpecies) {
+                    const uint64_t bit = 1ull << (4 * d + k);
+                    atomicOr(reinterpret_cast<unsigned long long*>(&mk[e * 64 + lane]), (unsigned long long)bit);
+                    mm |= bit;
+                } else {
+                    ok = false;
+                }
+            }
+        }
+    if (__ballot(!ok)) return false;
+    wave_lds_order();
+    uint64_t rows[kRegSpecies];
+#pragma unroll
+    for (int e = 0; e < kRegSpecies; ++e) rows[e] = mk[e * 64 + lane];
+    int hv = kInf;
+#pragma unroll
+    for (int e = 0; e < kRegSpecies; ++e) {
+        const uint64_t m = __ballot(rows[e] != 0);
+        if (m) {
+            const int l = (int)__ffsll((long long)m) - 1;
+            const uint64_t v = readlane64(rows[e], l);
+            if (lane == e) hv = l * 64 + (int)__ffsll((long long)v) - 1;
+        }
+    }
+    const int nw = (len + 63) >> 6;
+    for (int w = 0; w < nw; ++w) {
+        uint64_t cur = readlane64(mm, w);
+        if (!cur) continue;
+        // coins of the chunk: lane j draws position 64 w + j
+        const int xj = w * 64 + lane;
+        const bool coin = xj < len && (philox((uint32_t)spos_s[xj], c, g, TAG_X, seed).x >> 31) != 0;
+        const uint64_t xm = __ballot(coin);
+        while (cur) {
+            const int po = (int)__ffsll((long long)cur) - 1;
+            cur &= cur - 1;
+            const int p = w * 64 + po;
+            const int a = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)R[po >> 2], w), po & 3);
+            const int b = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)Bv[po >> 2], w), po & 3);
+            const int q = __builtin_amdgcn_readlane(hv, b);
+            if (q >= len || q <= p) return false;
+            const int qw = q >> 6, qo = q & 63;
+            const int bq = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)Bv[qo >> 2], qw), qo & 3);
+            const bool carry = bq != a;   // q keeps disagreeing with B after taking a
+            const uint64_t bitq = 1ull << qo, bitp = 1ull << po;
+            // row of b loses q; its new head is the first set bit from lane qw on
+            uint64_t rb = rows[b];
+            rb = lane == qw ? rb & ~bitq : rb;
+            rows[b] = rb;
+            int hb = kInf;
+            {
+                const uint64_t m = __ballot(lane >= qw && rb != 0);
+                if (m) {
+                    const int l = (int)__ffsll((long long)m) - 1;
+                    hb = l * 64 + (int)__ffsll((long long)readlane64(rb, l)) - 1;
+                }
+            }
+            // row of a loses p and gains q when q keeps disagreeing
+            uint64_t ra = rows[a];
+            ra = lane == w ? ra & ~bitp : ra;
+            if (carry) ra = lane == qw ? ra | bitq : ra;
+            rows[a] = ra;
+            int ha = kInf;
+            {
+                const uint64_t m = __ballot(lane >= w && ra != 0);
+                if (m) {
+                    const int l = (int)__ffsll((long long)m) - 1;
+                    ha = l * 64 + (int)__ffsll((long long)readlane64(ra, l)) - 1;
+                }
+            }
+            hv = lane == b ? hb : hv;
+            hv = lane == a ? ha : hv;
+            // ref[q] = a
+            {
+                const uint32_t sh = 8u * (uint32_t)(qo & 3);
+                const uint32_t v = R[qo >> 2];
+                const uint32_t nv = (v & ~(0xffu << sh)) | ((uint32_t)a << sh);
+                R[qo >> 2] = lane == qw ? nv : v;
+            }
+            if (!carry) {
+                if (qw == w) cur &= ~bitq;
+                else mm = lane == qw ? mm & ~bitq : mm;
+            }
+            // the child takes this swap of the path with probability 1/2
+            if ((xm >> po) & 1) {
+                const uint32_t vp = Cv[po >> 2], vq = Cv[qo >> 2];
+                const uint32_t cp = byte_of((uint32_t)__builtin_amdgcn_readlane((int)vp, w), po & 3);
+                const uint32_t cq = byte_of((uint32_t)__builtin_amdgcn_readlane((int)vq, qw), qo & 3);
+                const uint32_t shp = 8u * (uint32_t)(po & 3), shq = 8u * (uint32_t)(qo & 3);
+                Cv[po >> 2] = lane == w ? (vp & ~(0xffu << shp)) | (cq << shp) : vp;
+                const uint32_t vq2 = Cv[qo >> 2];
+                Cv[qo >> 2] = lane == qw ? (vq2 & ~(0xffu << shq)) | (cp << shq) : vq2;
+            }
+        }
+    }
+    // child bytes back to LDS
+#pragma unroll
+    for (int d = 0; d < 16; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * d + k;
+            if (x < len) cs[x] = (uint8_t)byte_of(Cv[d], k);
+        }
+    wave_lds_order();
+    return true;
+}
+
 // Child c of generation g (SI, "Genetic Algorithm"). Children below n_elite copy
 // the elites. Every other child draws parents A and B by roulette, crosses them
 // and may mutate:
@@ -215,6 +367,10 @@ __global__ __launch_bounds__(64) void k_ga_child(
         uint8_t* rs = rf + base;
         uint8_t* cs = ch + base;
         const uint8_t* bs = bb + base;
+        if (len <= kRegMaxLen && E <= kRegSpecies) {
+            crossover_regs(rs, cs, bs, len, spos + base, mk, (uint32_t)c, g, seed, lane);
+            continue;
+        }
         // bit rows: mk[e * Wd + w] bit l <=> position 64 w + l holds e and disagrees with B
         for (int w = 0; w < Wd; ++w) {
             const int x = w * 64 + lane;

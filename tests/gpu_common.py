@@ -18,6 +18,19 @@ def two_sublattice_cell():
     return S.make_cell(lat, pos, sub, spc, charge, names)
 
 
+def many_species_cell():
+    """Rock-salt 2x2x2 conventional cell whose 32 cation positions hold 20 species
+    (ids 0..19, all 2+: twelve with two ions, eight with one) over 32 fixed O2-;
+    more species than a register-resident crossover walk holds."""
+    lat, pos, kind = S.rocksalt_conventional(2, 2, 2, 4.2)
+    names = ["M%d" % e for e in range(20)] + ["O"]
+    charge = [2.0] * 20 + [-2.0]
+    sub = np.where(kind == 0, 0, -1).astype(np.int32)
+    spc = np.full(len(pos), 20, np.uint8)
+    spc[kind == 0] = np.array(sum(([e, e] for e in range(12)), []) + list(range(12, 20)), np.uint8)
+    return S.make_cell(lat, pos, sub, spc, charge, names)
+
+
 def swap_energy_difference(Vi, Vj, q, i, j):
     """E(q') - E(q) for q' = q with entries i and j exchanged, from rows i and j of
     the pair matrix only: with delta = q' - q (non-zero at i and j),

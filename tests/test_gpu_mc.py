@@ -10,7 +10,7 @@ import torch
 
 import oracle as O
 import supercells as S
-from gpu_common import two_sublattice_cell
+from gpu_common import many_species_cell, two_sublattice_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -235,9 +235,13 @@ def test_remc_exchange_bitexact(ctx, cfg1):
 
 # ------------------------------------------------------------------ GA
 
-@pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96)])
+@pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96),
+                                     ("config5", 24), ("many", 40)])
 def test_ga_generation_bitexact(ctx, which, P):
-    cell = two_sublattice_cell() if which == "two" else getattr(S, which)()
+    """Covers the register-resident crossover walk (sublattices of up to 4096
+    positions, up to 16 species) and the LDS walk (the 8192-position sublattice of
+    the 16384-site cell; the 20-species cell)."""
+    cell = {"two": two_sublattice_cell, "many": many_species_cell}.get(which, getattr(S, which, None))()
     V = torch.zeros((len(cell["pos"]),) * 2, dtype=torch.float64)
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
     pop = O.init_occupations(cell, P, seed=1)
