@@ -67,6 +67,7 @@ def lib():
         L.or_mc_run.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int64, P, P, P, P,
                                 C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
                                 P, C.c_int32, C.c_uint64, P, C.c_int32]
+        L.or_gd_run.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int64, P, C.c_int64, C.c_double, P, P]
         L.or_remc_exchange.argtypes = [C.c_int32, P, P, P, C.c_uint64, C.c_uint64, C.c_uint32, P]
         L.or_ga_generation.argtypes = [C.c_int64, P, C.c_int32, C.c_int64, P, P, C.c_uint64,
                                        C.c_uint32, C.c_int32, C.c_double, P]
@@ -215,6 +216,22 @@ def mc_run(V, cell, state: MCState, seed, n_trials, kT, block_len, chain_base=0,
     if rc:
         raise ValueError("oracle MC failed")
     return state
+
+
+def gd_run(V, cell, occ, max_steps=1 << 30, tol=1e-9):
+    """Best-swap descent of each row of ``occ`` (SI, "Gradient Descent"); returns
+    (local minima, swaps taken, energies)."""
+    V = _c(V, np.float64)
+    sub = _c(cell["sublattice"], np.int32)
+    charge = _c(cell["charge"], np.float64)
+    occ = _c(np.atleast_2d(occ), np.uint8).copy()
+    P, n = occ.shape
+    steps = np.zeros(P, np.int64)
+    E = np.zeros(P, np.float64)
+    rc = lib().or_gd_run(_p(V), n, _p(sub), _p(charge), len(charge), P, _p(occ), max_steps, tol, _p(steps), _p(E))
+    if rc:
+        raise ValueError("oracle gradient descent failed")
+    return occ, steps, E
 
 
 def remc_exchange(kT_ladder, E, slot, x, seed, group=0):

@@ -21,6 +21,8 @@
  *   or_init_occupations ...... random valid start (SI, "Random")
  *   or_mc_run ................ Metropolis / annealed swap Monte Carlo (SI, "Monte
  *                              Carlo" and "Simulated annealing")
+ *   or_gd_run ................ best-swap descent to a local minimum (SI,
+ *                              "Gradient Descent")
  *   or_remc_exchange ......... replica-exchange step (SI, "Replica Exchange MC")
  *   or_ga_generation ......... genetic algorithm generation (SI, "Genetic
  *                              Algorithm": roulette, swap crossover, mutation,
@@ -506,6 +508,80 @@ int or_mc_run(const double* V, int64_t n, const int32_t* sub, const double* char
         S->t += n_trials;
         S->E = E;
         free(where); free(q); free(phi);
+        prob_free(&pb);
+    }
+    return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gradient descent (SI, "Gradient Descent"): from each start, every neighbour  */
+/* reachable by one swap of two ions of different species on the same site      */
+/* class is scored by dE (the Monte Carlo trial's expression, with the field     */
+/* phi_k = sum_l V_kl q_l over all sites) and the best one is applied, until no  */
+/* neighbour lies lower. Reading of "the lowest-energy neighbour": among the     */
+/* swaps (i, j), i < j in mobile order, whose dE lies within tol of the lowest   */
+/* dE, the lexicographically smallest; symmetry-equivalent neighbours have equal */
+/* energies that any implementation only resolves to rounding noise, and the    */
+/* window makes the choice independent of it. Descent stops when the lowest dE  */
+/* is >= -tol (a local minimum) or after max_steps swaps.                        */
+/* ------------------------------------------------------------------------- */
+int or_gd_run(const double* V, int64_t n, const int32_t* sub, const double* charge, int32_t n_species,
+              int64_t P, uint8_t* occ, int64_t max_steps, double tol, int64_t* steps, double* E_out) {
+    if (!(tol >= 0.0) || max_steps < 0) return -1;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t p = 0; p < P; ++p) {
+        uint8_t* o = occ + p * n;
+        prob_t pb;
+        if (prob_setup(&pb, n, sub, o, n_species)) { err |= 1; continue; }
+        const int64_t M = pb.M;
+        double* q = (double*)malloc(sizeof(double) * (size_t)n);
+        double* phi = (double*)malloc(sizeof(double) * (size_t)(M ? M : 1));
+        for (int64_t i = 0; i < n; ++i) q[i] = charge[o[i]];
+        for (int64_t k = 0; k < M; ++k) {
+            double f = 0.0;
+            for (int64_t l = 0; l < n; ++l) f += V[pb.mob[k] * n + l] * q[l];
+            phi[k] = f;
+        }
+        double E = or_energy_q(V, n, q);
+        int64_t st = 0;
+        while (st < max_steps) {
+            /* lowest dE over all neighbours */
+            double lo = INFINITY;
+            for (int64_t i = 0; i < M; ++i)
+                for (int64_t j = i + 1; j < M; ++j) {
+                    const int64_t si = pb.mob[i], sj = pb.mob[j];
+                    if (pb.msub[i] != pb.msub[j] || o[si] == o[sj]) continue;
+                    const double d = charge[o[sj]] - charge[o[si]];
+                    const double dE = d * (phi[i] - phi[j]) +
+                                      0.5 * d * d * (V[si * n + si] + V[sj * n + sj] - 2.0 * V[si * n + sj]);
+                    if (dE < lo) lo = dE;
+                }
+            if (!(lo < -tol)) break;
+            /* first swap (lexicographic) within tol of the lowest */
+            int64_t bi = -1, bj = -1;
+            double bdE = 0.0;
+            for (int64_t i = 0; i < M && bi < 0; ++i)
+                for (int64_t j = i + 1; j < M; ++j) {
+                    const int64_t si = pb.mob[i], sj = pb.mob[j];
+                    if (pb.msub[i] != pb.msub[j] || o[si] == o[sj]) continue;
+                    const double d = charge[o[sj]] - charge[o[si]];
+                    const double dE = d * (phi[i] - phi[j]) +
+                                      0.5 * d * d * (V[si * n + si] + V[sj * n + sj] - 2.0 * V[si * n + sj]);
+                    if (dE <= lo + tol) { bi = i; bj = j; bdE = dE; break; }
+                }
+            const int64_t si = pb.mob[bi], sj = pb.mob[bj];
+            const uint8_t a = o[si], b = o[sj];
+            const double d = charge[b] - charge[a];
+            o[si] = b; o[sj] = a;
+            q[si] = charge[b]; q[sj] = charge[a];
+            for (int64_t kk = 0; kk < M; ++kk) phi[kk] += d * (V[si * n + pb.mob[kk]] - V[sj * n + pb.mob[kk]]);
+            E += bdE;
+            ++st;
+        }
+        steps[p] = st;
+        E_out[p] = E;
+        free(q); free(phi);
         prob_free(&pb);
     }
     return err ? -1 : 0;
