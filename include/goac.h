@@ -277,6 +277,27 @@ goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_i
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
 
+/* ---------------------------------------------------------------- gradient descent */
+
+/* Best-swap descent of P configurations to local minima (SI, "Gradient
+ * Descent"). A step scores every swap of two positions of one site class that hold
+ * different species by dE = d (phi_i - phi_j) + 1/2 d^2 (V_ii + V_jj - 2 V_ij),
+ * d = q_j - q_i, with the FP64 field phi = V_mm q + h, and applies the
+ * lexicographically first swap (i < j in mobile order) among those whose dE lies
+ * within tol of the lowest dE (equal-energy neighbours are resolved only to
+ * rounding noise, so the window makes the choice well defined); it stops when the
+ * lowest dE is >= -tol or after max_steps swaps.
+ *   occ_dev   : P x n uint8, read and overwritten with the local minima (fixed
+ *               sites are left as they are; ids >= n_species are read as the last
+ *               species, as in goac_energies)
+ *   max_steps : swaps per configuration at most; tol >= 0 (eV), e.g. 1e-9
+ *   steps_dev : P int64 output (swaps taken) or NULL
+ *   E_dev     : P FP64 output (energy of the result) or NULL
+ * One workgroup holds a configuration's mobile block: EINVAL when 18 bytes per
+ * mobile position exceed the compute unit's shared memory. */
+goac_status goac_gd_run(goac_problem* pb, int64_t P, uint8_t* occ_dev, int64_t max_steps, double tol,
+                        int64_t* steps_dev, double* E_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,7 +63,7 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_problem_create", "goac_problem_destroy", "goac_problem_get_info", "goac_init_occupations",
             "goac_energies", "goac_topk_fp64", "goac_chains_create", "goac_chains_destroy",
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
-            "goac_remc_exchange", "goac_ga_generation"]
+            "goac_remc_exchange", "goac_ga_generation", "goac_gd_run"]
 
 
 def load():
@@ -95,6 +95,7 @@ def load():
         "goac_chains_export": ([P, P, P, P], I32),
         "goac_remc_exchange": ([P, I32, P, U64, U64, P, P], I32),
         "goac_ga_generation": ([P, I64, P, P, P, P], I32),
+        "goac_gd_run": ([P, I64, P, I64, C.c_double, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -210,6 +211,16 @@ class Problem:
         prm = GAParams(seed, generation, n_elite, p_mut)
         self.ctx.check(load().goac_ga_generation(self._h, P, _ptr(pop), _ptr(E), C.byref(prm), _ptr(o)))
         return o
+
+    def gd_run(self, occ, max_steps=1 << 40, tol=1e-9):
+        """Best-swap descent of each row of occ (modified in place, on the device);
+        returns (occ, steps, E)."""
+        occ = _dev(occ, torch.uint8, self.ctx.device)
+        P = occ.shape[0] if occ.dim() > 1 else 1
+        steps = torch.empty(P, dtype=torch.int64, device=occ.device)
+        E = torch.empty(P, dtype=torch.float64, device=occ.device)
+        self.ctx.check(load().goac_gd_run(self._h, P, _ptr(occ), max_steps, tol, _ptr(steps), _ptr(E)))
+        return occ, steps, E
 
     def close(self):
         if getattr(self, "_h", None):
