@@ -194,6 +194,22 @@ class MCState:
         return np.array([getattr(s, name) for s in self.stats])
 
 
+def mc_reload(state: "MCState", V, charge, occ):
+    """Continue the chains of ``state`` from new occupations: counters and trial
+    indices kept, energies recomputed, the best replaced where the new occupation
+    is strictly lower; the next mc_run rebuilds the position lists."""
+    occ = np.asarray(occ, np.uint8)
+    E = energies(V, occ, charge)
+    for c in range(len(occ)):
+        state.stats[c].E = E[c]
+        if E[c] < state.stats[c].best_E:
+            state.stats[c].best_E = E[c]
+            state.best_occ[c] = occ[c]
+    state.occ[:] = occ
+    state.reload = True
+    return state
+
+
 def mc_run(V, cell, state: MCState, seed, n_trials, kT, block_len, chain_base=0, instance=0,
            kT_row=None):
     """Advance every chain in ``state`` by n_trials trials (resumable)."""
@@ -212,7 +228,9 @@ def mc_run(V, cell, state: MCState, seed, n_trials, kT, block_len, chain_base=0,
     rc = lib().or_mc_run(_p(V), n, _p(sub), _p(charge), len(charge), C_, _p(state.occ),
                          _p(state.perm), _p(state.best_occ), C.cast(state.stats, C.c_void_p),
                          seed, chain_base, instance, n_trials, _p(kT), nb, block_len,
-                         None if rows is None else _p(rows), 1 if init else 0)
+                         None if rows is None else _p(rows),
+                         1 if init else (2 if getattr(state, "reload", False) else 0))
+    state.reload = False
     if rc:
         raise ValueError("oracle MC failed")
     return state
@@ -266,6 +284,56 @@ def topk(V, occ, charge, k):
     E = np.zeros(kk, np.float64)
     lib().or_topk(_p(V), n, P, _p(occ), _p(charge), k, _p(idx), _p(E))
     return idx, E
+
+
+def hybrid_round(V, cell, state, slot, pop, r, R, kT, trials, exchanges, generations, n_elite, p_mut, seed,
+                 inject):
+    """One round of the replica-exchange + GA hybrid (SI, "Hybrid Methods": the
+    two heuristics run alternately and hand their best solutions on). Reading:
+      1. REMC phase: `exchanges` times, every chain runs `trials` trials at the
+         temperature of its slot, then one exchange step x = r exchanges + e in
+         every group of R consecutive chains;
+      2. REMC -> GA: the population becomes the P lowest, by (FP64 energy, index),
+         of the population followed by the chains' best occupations;
+      3. GA phase: `generations` generations g = r generations + k, each followed
+         by FP64 energies of the children;
+      4. GA -> REMC: the coldest replica of group k takes the individual of rank
+         k mod min(inject, P) (order (E, index)) when that individual is strictly
+         lower than the replica's current energy; all chains continue from their
+         (possibly new) occupations.
+    ``state`` (MCState), ``slot`` (groups x R) and the returned population carry
+    over between rounds. Returns (population, its energies, slot)."""
+    charge = np.asarray(cell["charge"], np.float64)
+    kT = np.asarray(kT, np.float64)
+    C = len(state.occ)
+    G = C // R
+    P = len(pop)
+    slot = np.array(slot, np.int32).reshape(G, R)
+    for e in range(exchanges):
+        rows = np.empty(C, np.int32)
+        for g in range(G):
+            rows[g * R + slot[g]] = np.arange(R)
+        mc_run(V, cell, state, seed=seed, n_trials=trials, kT=kT[:, None], block_len=trials, kT_row=rows)
+        E = state.field("E")
+        for g in range(G):
+            slot[g], _ = remc_exchange(kT, E[g * R:(g + 1) * R], slot[g], r * exchanges + e, seed, group=g)
+    cand = np.concatenate([np.asarray(pop, np.uint8), state.best_occ])
+    idx, E = topk(V, cand, charge, P)
+    pop = cand[idx]
+    for k in range(generations):
+        pop = ga_generation(cell, pop, E, seed=seed, g=r * generations + k, n_elite=n_elite, p_mut=p_mut)
+        E = energies(V, pop, charge)
+    n_inj = max(1, min(inject, P))
+    order = np.lexsort((np.arange(P), E))[:n_inj]
+    occ = state.occ.copy()
+    Ech = state.field("E")
+    for g in range(G):
+        c = g * R + slot[g][0]
+        i = order[g % n_inj]
+        if E[i] < Ech[c]:
+            occ[c] = pop[i]
+    mc_reload(state, V, charge, occ)
+    return pop, E, slot
 
 
 def num_threads():

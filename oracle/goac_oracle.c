@@ -417,6 +417,9 @@ int or_init_occupations(int64_t n, const int32_t* sub, const uint8_t* species, i
 /*   on accept: swap occ, swap the two perm entries, phi_k += d (V_ik - V_jk)    */
 /*   for all mobile k when d != 0, E += dE, best kept on strict improvement      */
 /*   hash += splitmix64(splitmix64(t) ^ (i << 33 | j << 1 | accepted))           */
+/* init_perm: 1 starts the chains (counters zero, best = start); 0 resumes them; */
+/* 2 reloads them from new occupations (counters and trial index kept, position  */
+/* lists rebuilt, best replaced only by a strictly lower start).                 */
 /* ------------------------------------------------------------------------- */
 typedef struct {
     uint64_t t;          /* trials done so far                                  */
@@ -443,9 +446,11 @@ int or_mc_run(const double* V, int64_t n, const int32_t* sub, const double* char
         const int64_t M = pb.M;
         int32_t* pm = perm + ch * (M ? M : 1);
         or_chain_stats* S = &st[ch];
-        if (init_perm) {
+        if (init_perm == 1) {
             perm_sorted(&pb, o, pm);
             memset(S, 0, sizeof(*S));
+        } else if (init_perm == 2) {
+            perm_sorted(&pb, o, pm);   /* reload: new occupation, counters kept */
         }
         int32_t* where = (int32_t*)malloc(sizeof(int32_t) * (size_t)(M ? M : 1));
         for (int64_t k = 0; k < M; ++k) where[pm[k]] = (int32_t)k;
@@ -458,7 +463,7 @@ int or_mc_run(const double* V, int64_t n, const int32_t* sub, const double* char
             phi[k] = f;
         }
         double E = or_energy_q(V, n, q);
-        if (init_perm) {
+        if (init_perm == 1 || (init_perm == 2 && E < S->best_E)) {
             S->best_E = E;
             memcpy(best_occ + ch * n, o, (size_t)n);
         }

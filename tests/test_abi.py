@@ -2,6 +2,7 @@
 declares; the Python binding refuses to run without it. No device calls."""
 import ctypes
 import os
+import subprocess
 import re
 
 import pytest
@@ -51,12 +52,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         G.load()
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's structures have the size and field offsets that a C compiler
+    gives the header's."""
     import paper_2409_08808_amd as G
-    assert ctypes.sizeof(G.MCParams) == 56
-    assert ctypes.sizeof(G.GAParams) == 24
-    assert ctypes.sizeof(G.EwaldParams) == 24
-    assert G.STATS_DTYPE.itemsize == 72
+    structs = {"goac_mc_params": G.MCParams, "goac_ga_params": G.GAParams, "goac_ewald_params": G.EwaldParams,
+               "goac_hybrid_params": G.HybridParams, "goac_problem_info": G.ProblemInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "goac.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append('printf("goac_chain_stats %zu\\n", sizeof(goac_chain_stats));')
+    for f in G.STATS_DTYPE.names:
+        lines.append('printf("goac_chain_stats.%s %%zu\\n", offsetof(goac_chain_stats, %s));' % (f, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
+    assert int(got["goac_chain_stats"]) == G.STATS_DTYPE.itemsize
+    for f in G.STATS_DTYPE.names:
+        assert int(got["goac_chain_stats.%s" % f]) == G.STATS_DTYPE.fields[f][1], f
 
 
 def test_product_path_does_not_reference_the_oracle():
