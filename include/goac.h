@@ -247,7 +247,8 @@ goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_
  * Configurations stay with their chains; the chains' temperature rows move.
  *   slot_dev : (C / R) x R int32, the chain (index within its group) at each
  *              temperature, in/out
- *   acc_dev  : (C / R) x R uint8 accepted flags per lower index k (may be NULL)
+ *   acc_dev  : (C / R) x R uint8: 1 where the pair (k, k+1) attempted at this step
+ *              was accepted, 0 elsewhere (may be NULL)
  * Sweeps after an exchange run chain c at row = its temperature index. */
 goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host, uint64_t x,
                                uint64_t seed, int32_t* slot_dev, uint8_t* acc_dev);
@@ -276,6 +277,54 @@ typedef struct {
 goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
+
+/* Continue every chain from new occupations (occ_dev: C x n, device), e.g. to hand
+ * it a configuration found by another heuristic. Trial counters, counts, hash and
+ * temperature rows are kept; the position lists, field and energy are rebuilt
+ * (an FP64 anchor); the best energy and occupation are replaced only when the new
+ * occupation is strictly lower. Each occupation must keep the problem's
+ * composition (EINVAL otherwise; the check synchronises). */
+goac_status goac_chains_load(goac_chains* ch, const uint8_t* occ_dev);
+
+/* ---------------------------------------------------------------- hybrid REMC + GA */
+
+typedef struct {
+    uint64_t seed;
+    uint64_t round;            /* round index r (exchange steps and generations
+                                  continue across rounds)                          */
+    int64_t trials;            /* trials per chain before each exchange step        */
+    const double* kT_host;     /* R temperatures (eV), ascending                    */
+    int32_t R;                 /* replicas per group of consecutive chains          */
+    int32_t exchanges;         /* exchange steps per REMC phase                     */
+    int32_t generations;       /* GA generations per GA phase                       */
+    int32_t n_elite;
+    double p_mut;
+    int32_t inject;            /* GA ranks handed to the groups' coldest replicas   */
+    int32_t precision;         /* goac_precision of the GA phase's energies         */
+    int32_t reanchor_every;    /* MIXED chains: as in goac_mc_params (0: 1024)      */
+    int32_t reserved;
+} goac_hybrid_params;
+
+/* One round of the replica-exchange + GA hybrid (SI, "Hybrid Methods": the two
+ * heuristics run alternately and hand their best solutions on):
+ *   1. REMC phase: `exchanges` times, every chain runs `trials` trials at the
+ *      temperature of its slot, then one exchange step x = r exchanges + e;
+ *   2. REMC -> GA: the population becomes the P lowest, by (FP64 energy, index),
+ *      of the population followed by the chains' best occupations;
+ *   3. GA phase: `generations` generations g = r generations + k, each followed by
+ *      the children's energies in the requested precision;
+ *   4. GA -> REMC: the coldest replica of group k takes the individual of rank
+ *      k mod min(inject, P) when that individual is strictly lower than the
+ *      replica's current energy; all chains continue (goac_chains_load).
+ *   ch       : chains of one problem, C = groups x R
+ *   slot_dev : groups x R int32 as in goac_remc_exchange (in/out); the chains'
+ *              rows are set from it at the start
+ *   pop_dev  : P x n population (in/out); E_dev : P FP64, the energies of the
+ *              returned population (out)
+ * Synchronises (composition check of the reload). The chain set owns the scratch
+ * memory of the round (grown on demand, freed with the chains). */
+goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int64_t P, uint8_t* pop_dev, double* E_dev,
+                              const goac_hybrid_params* params);
 
 /* ---------------------------------------------------------------- gradient descent */
 

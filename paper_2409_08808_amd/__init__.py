@@ -52,6 +52,13 @@ class GAParams(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("generation", C.c_uint32), ("n_elite", C.c_int32), ("p_mut", C.c_double)]
 
 
+class HybridParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("round", C.c_uint64), ("trials", C.c_int64), ("kT_host", C.c_void_p),
+                ("R", C.c_int32), ("exchanges", C.c_int32), ("generations", C.c_int32), ("n_elite", C.c_int32),
+                ("p_mut", C.c_double), ("inject", C.c_int32), ("precision", C.c_int32),
+                ("reanchor_every", C.c_int32), ("reserved", C.c_int32)]
+
+
 # goac_chain_stats
 STATS_DTYPE = np.dtype([("t", "<u8"), ("accepts", "<u8"), ("updates", "<u8"), ("hash", "<u8"),
                         ("fallbacks", "<u8"), ("anchors", "<u8"), ("E", "<f8"), ("best_E", "<f8"),
@@ -63,7 +70,8 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_problem_create", "goac_problem_destroy", "goac_problem_get_info", "goac_init_occupations",
             "goac_energies", "goac_topk_fp64", "goac_chains_create", "goac_chains_destroy",
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
-            "goac_remc_exchange", "goac_ga_generation", "goac_gd_run"]
+            "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
+            "goac_hybrid_round"]
 
 
 def load():
@@ -96,6 +104,8 @@ def load():
         "goac_remc_exchange": ([P, I32, P, U64, U64, P, P], I32),
         "goac_ga_generation": ([P, I64, P, P, P, P], I32),
         "goac_gd_run": ([P, I64, P, I64, C.c_double, P, P], I32),
+        "goac_chains_load": ([P, P], I32),
+        "goac_hybrid_round": ([P, P, I64, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -300,6 +310,23 @@ class Chains:
         kT = _np(kT_ladder, np.float64)
         self.ctx.check(load().goac_remc_exchange(self._h, R, kT.ctypes.data_as(C.c_void_p), x, seed,
                                                  _ptr(slot), _ptr(acc)))
+
+    def load(self, occ):
+        """Continue every chain from new occupations (counters and rows kept)."""
+        occ = _dev(occ, torch.uint8, self.ctx.device)
+        self.ctx.check(load().goac_chains_load(self._h, _ptr(occ)))
+
+    def hybrid_round(self, slot, pop, R, kT, trials, exchanges, generations, seed, round, n_elite=8, p_mut=0.2,
+                     inject=8, precision=GOAC_MIXED, reanchor_every=1024, E_out=None):
+        """One REMC + GA hybrid round; pop (P x n, device) and slot are updated in
+        place. Returns the energies of the returned population."""
+        kT = _np(kT, np.float64)
+        P = pop.shape[0]
+        E = E_out if E_out is not None else torch.empty(P, dtype=torch.float64, device=pop.device)
+        prm = HybridParams(seed, round, trials, kT.ctypes.data_as(C.c_void_p), R, exchanges, generations, n_elite,
+                           p_mut, inject, precision, reanchor_every, 0)
+        self.ctx.check(load().goac_hybrid_round(self._h, _ptr(slot), P, _ptr(pop), _ptr(E), C.byref(prm)))
+        return E
 
     def close(self):
         if getattr(self, "_h", None):

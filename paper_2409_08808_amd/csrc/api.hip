@@ -10,8 +10,6 @@
 namespace goac {
 
 goac_status build_ewald(goac_ctx*, const double*, int64_t, const double*, const goac_ewald_params*, double*);
-goac_status energies_mixed(goac_problem*, int64_t, const uint8_t*, double*);
-goac_status energies_fp64(goac_problem*, int64_t, const uint8_t*, double*);
 
 __global__ void k_init(int64_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
                        int32_t, const uint8_t*, uint64_t, uint32_t, uint32_t, uint8_t*);
@@ -20,7 +18,6 @@ __global__ void k_ga_child(int64_t, int32_t, int32_t, int32_t, const int32_t*, c
                            const uint8_t*, const int32_t*, const int32_t*, int32_t, const uint8_t*, int64_t,
                            const uint8_t*, const uint64_t*, const int32_t*, int32_t, uint64_t, uint32_t, double,
                            uint8_t*);
-goac_status rank_select(goac_ctx*, int64_t, const double*, int32_t, int32_t*, int64_t*, int32_t*, double*);
 goac_status anchor_batched(goac_ctx*, goac_chains*, int, uint32_t);
 constexpr int kInlineAnchorMaxMp = 1024;
 
@@ -210,7 +207,8 @@ __global__ void k_check_comp(int64_t n, int32_t M, int32_t S, int32_t E, const i
 }
 
 // mobile occupation, perm (positions of each sublattice sorted by (species,
-// position)) and the best copy of one chain; one wavefront per chain. Within a
+// position)) and, unless best is NULL, the best copy of one chain; one
+// wavefront per chain. Within a
 // 64-position chunk the rank of a position among equal (sublattice, species)
 // keys is a popcount of a ballot; running counts carry across chunks.
 __global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_t Mp, int32_t S, int32_t E,
@@ -236,7 +234,7 @@ __global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_
         const int s = mobile ? msub[k] : 0;
         const int key = (mobile && e < E) ? s * E + e : -1;
         occ_m[off + k] = (uint8_t)e;
-        best[off + k] = (uint8_t)e;
+        if (best) best[off + k] = (uint8_t)e;
         if (!mobile) perm[off + k] = 0;
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         // each distinct key of the chunk in turn (uniform loop)
@@ -259,15 +257,19 @@ __global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_
 
 // field and energy of every chain of one instance from Phi = Q V_mm (FP64):
 // phi = Phi + h; E = E_ff + 1/2 sum q (phi + h); MIXED stores phi - phibar_s in
-// FP32 with its error bound
+// FP32 with its error bound. A start sets the best energy; a reload keeps the
+// best (energy and occupation) unless the new occupation is strictly lower.
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_chain_field(int32_t M, int32_t Mp, const double* __restrict__ Q,
                                                      const double* __restrict__ Phi, const double* __restrict__ h,
                                                      const double* __restrict__ rowabs, double qmax,
                                                      const uint8_t* __restrict__ msub,
                                                      const double* __restrict__ phibar, double E_ff, int64_t first,
-                                                     ChainScalars* __restrict__ sc, void* __restrict__ phi) {
+                                                     ChainScalars* __restrict__ sc, void* __restrict__ phi,
+                                                     int reload, const uint8_t* __restrict__ occ_m,
+                                                     uint8_t* __restrict__ best) {
     __shared__ double s_a[256], s_b[256], s_c[256];
+    __shared__ int s_copy;
     const int64_t c = blockIdx.x;
     ChainScalars* S = sc + first + c;
     const int64_t off = S->off;
@@ -300,7 +302,12 @@ __global__ __launch_bounds__(256) void k_chain_field(int32_t M, int32_t Mp, cons
     if (threadIdx.x == 0) {
         const double E = E_ff + 0.5 * s_a[0];
         S->E = E;
-        S->best_E = E;
+        // a start sets the best; a reload replaces it only when strictly lower
+        const bool better = !reload || E < S->best_E;
+        if (better) S->best_E = E;
+        s_copy = reload && better;
+        S->since_anchor = 0;
+        S->status = 0;
         if (MIXED) {
             const double gM = (double)(M + 2) * 0x1p-53 * 1.01;
             S->eps = 0x1p-24 * s_b[0] * 1.0001 + gM * s_c[0] * 2.0;
@@ -312,6 +319,9 @@ __global__ __launch_bounds__(256) void k_chain_field(int32_t M, int32_t Mp, cons
             S->phibound = 0.0f;
         }
     }
+    __syncthreads();
+    if (s_copy)
+        for (int k = threadIdx.x; k < Mp; k += 256) best[off + k] = occ_m[off + k];
 }
 
 __global__ void k_export(int64_t n, int32_t M, const int32_t* __restrict__ mob, const int32_t* __restrict__ fixed_idx,
@@ -352,6 +362,8 @@ __global__ void k_remc(int64_t n_groups, int32_t R, const double* __restrict__ k
     const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gidx >= n_groups) return;
     int32_t* sl = slot + gidx * R;
+    if (acc)
+        for (int k = 0; k < R; ++k) acc[gidx * R + k] = 0;
     for (int k = 0; k < R; ++k)
         if ((uint32_t)sl[k] >= (uint32_t)R) return;    // not a permutation: left unchanged
     for (int k = (int)(x & 1u); k + 1 < R; k += 2) {
@@ -783,6 +795,8 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
 }
 
 // ------------------------------------------------------------------ chains
+static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload);
+
 static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     goac_ctx* ctx = ch->ctx;
     const int n_inst = (int)ch->pbs.size();
@@ -849,7 +863,18 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         return ch->pbs[ch->inst_of[a]]->d.Mp > ch->pbs[ch->inst_of[b]]->d.Mp;
     });
     GOAC_HIP(ctx, hipMemcpyAsync(base, host.data(), up_end, hipMemcpyHostToDevice, sm));
-    // composition check, setup and FP64 field, per instance
+    return chains_fill(ch, occ, false);
+}
+
+// composition check, setup (mobile occupation, position lists, best copy) and
+// FP64 field of every chain from occupations occ (instance after instance); a
+// reload keeps counters, rows and the best unless beaten. Synchronises to report
+// a broken composition.
+static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload) {
+    goac_ctx* ctx = ch->ctx;
+    const int n_inst = (int)ch->pbs.size();
+    hipStream_t sm = ctx->stream;
+    const bool mixed = ch->prec == GOAC_MIXED;
     void* sel = nullptr;
     GOAC_TRY(workspace(ctx, 2, 256, &sel));
     int32_t* err = (int32_t*)sel;
@@ -863,7 +888,8 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         hipLaunchKernelGGL(k_check_comp, dim3((unsigned)Ci), dim3(256), 0, sm, d.n, d.M, d.S, d.E, d.tab, d.mob,
                            d.msub, occ_i, err);
         hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)Ci), dim3(64), 0, sm, d.n, d.M, d.Mp, d.S, d.E, d.tab, d.mob,
-                           d.msub, occ_i, ch->first_chain[i], ch->d_offs, ch->occ, ch->perm, ch->best);
+                           d.msub, occ_i, ch->first_chain[i], ch->d_offs, ch->occ, ch->perm,
+                           reload ? nullptr : ch->best);
         const size_t qb = (size_t)round_up((int64_t)Ci * d.Mp * 8, 256);
         void* ws = nullptr;
         GOAC_TRY(workspace(ctx, 0, 2 * qb, &ws));
@@ -873,22 +899,33 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         GOAC_TRY(dgemm_nt(ctx, Ci, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr));
         if (mixed)
             hipLaunchKernelGGL(k_chain_field<true>, dim3((unsigned)Ci), dim3(256), 0, sm, d.M, d.Mp, Q, Phi, d.h,
-                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi);
+                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi,
+                               reload ? 1 : 0, ch->occ, ch->best);
         else
             hipLaunchKernelGGL(k_chain_field<false>, dim3((unsigned)Ci), dim3(256), 0, sm, d.M, d.Mp, Q, Phi, d.h,
-                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi);
+                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi,
+                               reload ? 1 : 0, ch->occ, ch->best);
         GOAC_CHECK_LAUNCH(ctx);
     }
     int32_t herr = 0;
     GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, sm));
     GOAC_HIP(ctx, hipStreamSynchronize(sm));
-    if (herr) return fail(ctx, GOAC_EINVAL, "chains_create: an occupation breaks the problem's composition");
+    if (herr) return fail(ctx, GOAC_EINVAL, "chains: an occupation breaks the problem's composition");
     return GOAC_OK;
 }
 
 static void chains_free(goac_chains* ch) {
     if (ch->arena) (void)hipFree(ch->arena);
     if (ch->kT) (void)hipFree(ch->kT);
+    if (ch->scratch) (void)hipFree(ch->scratch);
+}
+
+extern "C" goac_status goac_chains_load(goac_chains* ch, const uint8_t* occ_dev) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    if (!occ_dev) return fail(ctx, GOAC_EINVAL, "chains_load: bad arguments");
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    return chains_fill(ch, occ_dev, true);
 }
 
 extern "C" goac_status goac_chains_create(goac_problem* pb, int64_t C, const uint8_t* occ, goac_precision prec,
@@ -1092,14 +1129,14 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
     for (int k = 0; k < R; ++k)
         if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_exchange: kT must be positive");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    double* d = nullptr;
-    GOAC_HIP(ctx, hipMallocAsync((void**)&d, R * 8, ctx->stream));
+    void* ws = nullptr;
+    GOAC_TRY(workspace(ctx, 0, (size_t)R * 8, &ws));
+    double* d = (double*)ws;
     GOAC_HIP(ctx, hipMemcpyAsync(d, kT_host, R * 8, hipMemcpyHostToDevice, ctx->stream));
     const int64_t ng = ch->C / R;
     hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, ctx->stream, ng, R, d, x, seed, ch->sc,
                        slot, acc);
     GOAC_CHECK_LAUNCH(ctx);
-    GOAC_HIP(ctx, hipFreeAsync(d, ctx->stream));
     ch->max_row = std::max(ch->max_row, R - 1);
     return GOAC_OK;
 }

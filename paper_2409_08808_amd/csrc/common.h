@@ -211,6 +211,8 @@ struct goac_chains {
     std::vector<int64_t> count;       // chains per instance
     std::vector<int64_t> first_chain; // first chain of each instance
     std::vector<int64_t> occ_row_off; // byte offset of an instance's first occupation row
+    void* scratch = nullptr;          // hybrid rounds: candidate rows, energies, ranks (grown on demand)
+    size_t scratch_size = 0;
 };
 
 // ------------------------------------------------------------------ error helpers
@@ -262,6 +264,13 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
 
 // scratch memory of a context (grown, never shrunk)
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
+
+// population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies
+// by (E, index); cnt_scratch holds P int32
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
+goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
+goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, int32_t* cnt_scratch,
+                        int64_t* idx64, int32_t* idx32, double* Eout);
 
 // kernels shared across translation units
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,

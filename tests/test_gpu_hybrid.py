@@ -1,0 +1,92 @@
+"""GPU parity of the REMC + GA hybrid round (SI, "Hybrid Methods") and of the
+chain reload against the oracle. The pair matrix is a symmetric integer matrix
+on the 4x4x4 rock-salt geometry: every energy, field and energy difference is
+then an exact integer in FP64, FP32 and the bf16 split alike, so the roulette,
+ranking and hand-over decisions of both sides see identical numbers and the
+round is compared bit for bit (populations, slots, chain occupations, energies)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import supercells as S
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_2409_08808_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return G.Context(0)
+
+
+def _integer_pair_matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-4, 5, size=(n, n)).astype(np.float64)
+    return np.triu(A) + np.triu(A, 1).T
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_hybrid_rounds_match_oracle(ctx, prec):
+    cell = S.config2()
+    n = len(cell["pos"])
+    V = _integer_pair_matrix(n, 5)
+    R, groups, P = 4, 8, 48
+    ladder = np.array([0.5, 1.0, 2.0, 4.0])
+    occ0 = O.init_occupations(cell, R * groups, seed=2)
+    pop0 = O.init_occupations(cell, P, seed=3, chain_base=500)
+    # oracle
+    st = O.MCState(occ0)
+    pop_o, slot_o = pop0.copy(), np.tile(np.arange(R, dtype=np.int32), (groups, 1))
+    # GPU
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    ch = G.Chains(pb, torch.from_numpy(occ0), prec)
+    slot_g = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device="cuda")
+    pop_g = torch.from_numpy(pop0).cuda()
+    for r in range(3):
+        kw = dict(trials=300, exchanges=2, generations=2, n_elite=3, p_mut=0.4, seed=17)
+        pop_o, E_o, slot_o = O.hybrid_round(V, cell, st, slot_o, pop_o, r, R, ladder, inject=5, **kw)
+        E_g = ch.hybrid_round(slot_g, pop_g, R, ladder, round=r, inject=5, precision=prec, **kw)
+        assert np.array_equal(pop_g.cpu().numpy(), pop_o), "population differs in round %d" % r
+        assert np.array_equal(E_g.cpu().numpy(), E_o)
+        assert np.array_equal(slot_g.view(groups, R).cpu().numpy(), slot_o)
+        occ, best, stats = ch.export()
+        assert np.array_equal(occ.cpu().numpy(), st.occ)
+        assert np.array_equal(best.cpu().numpy(), st.best_occ)
+        assert np.array_equal(stats["E"], st.field("E"))
+        assert np.array_equal(stats["best_E"], st.field("best_E"))
+        assert np.array_equal(stats["accepts"], st.field("accepts"))
+        assert np.array_equal(stats["t"], st.field("t"))
+
+
+def test_chains_load_keeps_counters_and_best(ctx):
+    cell = S.config1()
+    V = O.cell_matrix(cell)
+    occ0 = O.init_occupations(cell, 8, seed=4)
+    ch = G.Chains(G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"]),
+                  torch.from_numpy(occ0), 0)
+    ch.sweep(2000, [0.05], seed=1)
+    _, best0, s0 = ch.export()
+    new = O.init_occupations(cell, 8, seed=99)
+    ch.load(torch.from_numpy(new))
+    occ, best, s1 = ch.export()
+    En = O.energies(V, new, cell["charge"])
+    assert np.array_equal(occ.cpu().numpy(), new)
+    assert np.array_equal(s1["t"], s0["t"]) and np.array_equal(s1["accepts"], s0["accepts"])
+    assert np.abs(s1["E"] - En).max() < 1e-9
+    lower = En < s0["best_E"]
+    assert np.allclose(s1["best_E"], np.where(lower, En, s0["best_E"]), atol=1e-9, rtol=0)
+    assert np.array_equal(best.cpu().numpy(), np.where(lower[:, None], new, best0.cpu().numpy()))
+    # the chains then continue exactly as the oracle's reloaded chains
+    st = O.MCState(occ0)
+    O.mc_run(V, cell, st, seed=1, n_trials=2000, kT=[0.05], block_len=10 ** 9)
+    O.mc_reload(st, V, cell["charge"], new)
+    O.mc_run(V, cell, st, seed=1, n_trials=1500, kT=[0.05], block_len=10 ** 9)
+    ch.sweep(1500, [0.05], seed=1, trace=False)
+    occ, best, s2 = ch.export()
+    assert np.array_equal(occ.cpu().numpy(), st.occ)
+    assert np.array_equal(s2["accepts"], st.field("accepts"))
+    assert np.abs(s2["best_E"] - st.field("best_E")).max() < 1e-9
