@@ -52,8 +52,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a copy kernel of known size")
     ap.add_argument("--ga-generations", type=int, default=200)
     ap.add_argument("--no-large", action="store_true", help="skip the 16384-site and 512-instance legs")
-    ap.add_argument("--only", default="", help="comma list of legs to run alone: fp64, ga, cfg5, cfg4, nacl "
-                                                "(the step itself always runs)")
+    ap.add_argument("--only", default="", help="comma list of legs to run alone: fp64, ga, cfg5, cfg4, nacl, "
+                                                "gd, remc, hybrid (the step itself always runs)")
     return ap.parse_args()
 
 
@@ -165,7 +165,7 @@ def main():
     }
     legs = set(args.only.split(",")) - {""}
     if not legs and not args.no_extras:
-        legs = {"fp64", "ga", "nacl"} | (set() if args.no_large else {"cfg5", "cfg4"})
+        legs = {"fp64", "ga", "nacl", "gd", "remc", "hybrid"} | (set() if args.no_large else {"cfg5", "cfg4"})
     if "fp64" in legs:
         w64, k64, s64 = timed(G.GOAC_FP64, max(2, args.steps // 2), 1)
         result["plain_fp64_trials_per_s"] = float(CHAINS) * TRIALS * max(2, args.steps // 2) / w64
@@ -179,6 +179,12 @@ def main():
         result.update(batched_instances(ctx, G, S, torch, stream))
     if "nacl" in legs:
         result.update(nacl_half(ctx, G, S, torch, stream))
+    if "gd" in legs:
+        result.update(gradient_descent(ctx, G, S, torch, stream))
+    if "remc" in legs:
+        result.update(replica_exchange(ctx, G, S, torch, stream))
+    if "hybrid" in legs:
+        result.update(hybrid(ctx, G, S, torch, stream))
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -341,6 +347,100 @@ def nacl_half(ctx, G, S, torch, stream):
             "nacl_madelung_best": float(-Eb.min() * 2.81 / ((n / 2) * K_E)),
             "nacl_madelung_of_order": float(-E_opt * 2.81 / ((n / 2) * K_E)),
             "nacl_fraction_at_optimum": float(np.mean(np.abs(Eb - E_opt) <= 1e-6 * n))}
+
+
+def gradient_descent(ctx, G, S, torch, stream):
+    """Best-swap descent of 4096 random starts of the 4x4x4 rock-salt cell to local
+    minima. A step scores all M (M - 1) / 2 pairs twice (lowest dE, then the first
+    pair within the window), reading the upper triangle of the FP64 V_mm each time."""
+    cell = S.config2()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    P, M = 4096, 256
+    occ = pb.init_occupations(P, seed=0)
+    pb.gd_run(occ.clone(), max_steps=2)                   # warm-up
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    occ, steps, E = pb.gd_run(occ)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    st = steps.cpu().numpy()
+    pb.close()
+    print("  [gd] %.3f s, %.1f swaps per start" % (sec, st.mean()), file=sys.stderr, flush=True)
+    pairs = (st.sum() + P) * 2.0 * M * (M - 1) / 2      # the final, non-improving step scores once
+    return {"gd_configs_per_s": P / sec, "gd_time_s": sec, "gd_swaps_per_start": float(st.mean()),
+            "gd_swaps_per_s": float(st.sum()) / sec, "gd_pair_evals_per_s": pairs / sec}
+
+
+def replica_exchange(ctx, G, S, torch, stream):
+    """Replica-exchange MC on the 4x4x4 rock-salt cell: 256 groups of 16 replicas on
+    a geometric ladder 0.02 -> 0.5 eV, 50 rounds of 2000 trials then one exchange
+    step (mixed field)."""
+    cell = S.config2()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    R, groups, rounds, per = 16, 256, 50, 2000
+    C = R * groups
+    ladder = np.geomspace(0.02, 0.5, R)
+    occ0 = pb.init_occupations(C, seed=0)
+    ch = G.Chains(pb, occ0, G.GOAC_MIXED)
+    ch.set_rows(np.tile(np.arange(R), groups))
+    slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
+    acc = torch.zeros(C, dtype=torch.uint8, device=occ0.device)
+    acc_sum = torch.zeros(C, dtype=torch.int64, device=occ0.device)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for x in range(rounds):
+        ch.sweep(per, ladder[:, None], per, seed=0)
+        ch.remc_exchange(R, ladder, x, 1, slot, acc)
+        acc_sum += acc
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    _, _, st = ch.export()
+    ch.close()
+    pb.close()
+    print("  [remc] %.3f s" % sec, file=sys.stderr, flush=True)
+    attempts = groups * sum(len(range(x % 2, R - 1, 2)) for x in range(rounds))
+    return {"remc_trials_per_s": C * rounds * per / sec, "remc_time_s": sec,
+            "remc_exchange_accept_rate": float(acc_sum.sum().item()) / attempts,
+            "remc_trial_accept_rate": float(st["accepts"].sum()) / (C * rounds * per),
+            "remc_best_E_min": float(st["best_E"].min())}
+
+
+def hybrid(ctx, G, S, torch, stream):
+    """REMC + GA hybrid on the 4x4x4 rock-salt cell: 256 groups of 16 replicas
+    (ladder 0.02 -> 0.5 eV, mixed field) and a population of 1024; 5 rounds of
+    (5 exchange steps after 1000 trials each, 10 GA generations with bf16
+    energies, hand-over of the 8 best)."""
+    cell = S.config2()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    R, groups, P, rounds = 16, 256, 1024, 5
+    ladder = np.geomspace(0.02, 0.5, R)
+    ch = G.Chains(pb, pb.init_occupations(R * groups, seed=0), G.GOAC_MIXED)
+    slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device="cuda")
+    pop = pb.init_occupations(P, seed=0, chain_base=1 << 20)
+    best = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(rounds):
+        E = ch.hybrid_round(slot, pop, R, ladder, trials=1000, exchanges=5, generations=10, seed=0, round=r,
+                            n_elite=8, p_mut=0.2, inject=8, precision=G.GOAC_MIXED)
+        best.append(float(E.min().item()))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ch.close()
+    pb.close()
+    print("  [hybrid] %.3f s" % sec, file=sys.stderr, flush=True)
+    trials = R * groups * 5 * 1000 * rounds
+    return {"hybrid_round_ms": 1e3 * sec / rounds, "hybrid_trials_per_s": trials / sec,
+            "hybrid_best_E_per_round": best}
 
 
 def cpu_baseline(S):

@@ -153,11 +153,17 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     double* chg = reinterpret_cast<double*>(tab + a.tab_max);
 
     if (tid == 0) s_flag = 0;
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_item = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int item = s_item;
+    for (int round = 0;; ++round) {
+        // a workgroup's first chain is its block index; later ones come from the
+        // work counter, used only when there are more chains than workgroups
+        int item = (int)blockIdx.x;
+        if (round > 0) {
+            if ((int)gridDim.x >= a.n_items) return;
+            __syncthreads();
+            if (tid == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            __syncthreads();
+            item = s_item;
+        }
         if (item >= a.n_items) return;
         const int c = a.order ? a.order[item] : item;
         ChainScalars* sc = a.sc + c;
