@@ -37,9 +37,9 @@ BF16_PEAK = 2.5e15
 # HBM bytes of one k_mc<mixed, 64> launch of this step from FETCH_SIZE and WRITE_SIZE,
 # each scaled by the same counter's reading for a 256 MiB copy (factors 2.0 and 1.0);
 # valid only for the kernel sources they were taken on (profiles/k_mc_rocksalt4x4x4_traffic.md)
-MC_TRAFFIC = {"bytes": 29089401.6,
+MC_TRAFFIC = {"bytes": 42580000.0,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": "1e34ce0adbfa7d6de9102e890521166b39d85837f3d78fe63bfdab3273bb0182"}
+              "sha256": "7598981162b62287f1d3f0e7d83c97de3795a5c1f8938425bd12c4d243771b70"}
 
 
 def parse():
