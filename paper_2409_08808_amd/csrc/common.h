@@ -27,18 +27,22 @@ __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
 // 32x32->64 products of counter words 0 and 2 with fixed multipliers, the high
 // halves xor-ed with the other counter words and the round key, which advances by
-// the Weyl constants after every round.
+// the Weyl constants after every round. Each three-way xor is one gfx950
+// three-input bitwise instruction (truth table 0x96, the parity of its inputs).
 struct u32x4 { uint32_t x, y, z, w; };
 
-__host__ __device__ inline u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint64_t seed) {
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ inline u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed) {
     uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -244,8 +244,8 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             const int na = cnt[s * E + sa];
             const int csz = subsize[s] - na;
             int j = i;
-            bool stop = false, unsure = false;
-            double d = 0.0, dE = 0.0;
+            bool stop = false;
+            double d = 0.0, dE = 0.0, e = 0.0, L32 = 0.0, m32 = 0.0;
             if (valid && csz > 0) {
                 const int k = (int)mulshift(r.y, (uint32_t)csz);
                 const int idx = k < offs[s * E + sa] ? k : k + na;
@@ -266,25 +266,15 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 const float u32 = ((float)ub + 0.5f) * 0x1p-24f;
                 const float lg = __builtin_amdgcn_logf(u32) * 0.693147182f;
                 const float kTf = (float)kT;
-                const double L32 = (double)(-kTf * lg);
-                const double m32 = ub < 2 ? INFINITY
-                                          : (double)(kTf * (0x1p-24f * __builtin_amdgcn_rcpf(u32) +
-                                                            0x1p-20f * (1.0f - lg)));
-                if constexpr (MIXED) {
-                    const double e = d != 0.0 ? 2.0 * fabs(d) * eps + kMargin : 0.0;
-                    const double hi = dE + e, lo = dE - e;
-                    const bool sure_acc = (hi <= 0.0) || (hi - L32 < -m32);
-                    const bool sure_rej = (lo > 0.0) && (lo - L32 > m32);
-                    unsure = !sure_acc && !sure_rej;
-                    stop = sure_acc || unsure;
-                } else {
-                    bool acc;
-                    if (dE <= 0.0) acc = true;
-                    else if (dE - L32 < -m32) acc = true;
-                    else if (dE - L32 > m32) acc = false;
-                    else acc = unit_open(r.z, r.w) < exp(-dE / kT);
-                    stop = acc;
-                }
+                L32 = (double)(-kTf * lg);
+                m32 = ub < 2 ? INFINITY
+                             : (double)(kTf * (0x1p-24f * __builtin_amdgcn_rcpf(u32) + 0x1p-20f * (1.0f - lg)));
+                // e bounds the FP32 field's error in dE (MIXED). The rule accepts iff
+                // dE < L (L > 0 covers dE <= 0), so a trial is surely rejected when
+                // dE - e > L32 + m32; every other trial stops the window and the first
+                // of them is resolved below.
+                if constexpr (MIXED) e = d != 0.0 ? 2.0 * fabs(d) * eps + kMargin : 0.0;
+                stop = !(dE - e > L32 + m32);
             }
             // first trial of the window that may be accepted
             const uint64_t mask = __ballot(stop);
@@ -308,7 +298,9 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 continue;
             }
             if (tid == f) {
-                s_b.i = i; s_b.j = j; s_b.unsure = unsure ? 1 : 0;
+                // sure accept: even dE + e lies below the threshold band
+                const bool sure = (dE + e <= 0.0) || (dE + e - L32 < -m32);
+                s_b.i = i; s_b.j = j; s_b.unsure = sure ? 0 : 1;
                 s_b.d = d; s_b.dE = dE; s_b.u = unit_open(r.z, r.w); s_b.kT = kT;
             }
             __syncthreads();
@@ -316,17 +308,20 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             const double bd = s_b.d;
             double bdE = s_b.dE;
             bool accf = true;
-            if (MIXED && s_b.unsure) {  // (never true for FP64)
-                // exact FP64 difference phi_i - phi_j from the occupation
-                double part = 0.0;
-                for (int k = tid; k < M; k += WG)
-                    part += (V64[(int64_t)bi * Mp + k] - V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
-                const double diff = wg_sum<WG>(part, s_scr) + (hv[bi] - hv[bj]);
-                const double Vii = diag[bi], Vjj = diag[bj];
-                const double Vij = V64[(int64_t)bi * Mp + bj];
-                bdE = bd * diff + 0.5 * bd * bd * (Vii + Vjj - 2.0 * Vij);
+            if (s_b.unsure) {
+                if constexpr (MIXED) {
+                    // exact FP64 difference phi_i - phi_j from the occupation
+                    double part = 0.0;
+                    for (int k = tid; k < M; k += WG)
+                        part += (V64[(int64_t)bi * Mp + k] - V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
+                    const double diff = wg_sum<WG>(part, s_scr) + (hv[bi] - hv[bj]);
+                    const double Vii = diag[bi], Vjj = diag[bj];
+                    const double Vij = V64[(int64_t)bi * Mp + bj];
+                    bdE = bd * diff + 0.5 * bd * bd * (Vii + Vjj - 2.0 * Vij);
+                    ++n_fb;
+                }
+                // the exact rule (the FP64 field's dE is exact already)
                 accf = (bdE <= 0.0) || (s_b.u < exp(-bdE / s_b.kT));
-                ++n_fb;
             }
             if (TRACE && tid == f) hsum += trial_hash(tl, (uint32_t)bi, (uint32_t)bj, accf ? 1u : 0u);
             if (accf) {
