@@ -378,7 +378,9 @@ def gradient_descent(ctx, G, S, torch, stream):
 def replica_exchange(ctx, G, S, torch, stream):
     """Replica-exchange MC on the 4x4x4 rock-salt cell: 256 groups of 16 replicas on
     a geometric ladder 0.02 -> 0.5 eV, 50 rounds of 2000 trials then one exchange
-    step (mixed field)."""
+    step (mixed field). Timed twice from the same start: rounds replayed from one
+    captured HIP graph (goac_remc_run, after autotuning the launch) and the same
+    rounds launched one call at a time."""
     cell = S.config2()
     V = ctx.build_ewald(cell["lattice"], cell["pos"])
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
@@ -386,31 +388,39 @@ def replica_exchange(ctx, G, S, torch, stream):
     C = R * groups
     ladder = np.geomspace(0.02, 0.5, R)
     occ0 = pb.init_occupations(C, seed=0)
-    ch = G.Chains(pb, occ0, G.GOAC_MIXED)
-    ch.set_rows(np.tile(np.arange(R), groups))
-    slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
-    acc = torch.zeros(C, dtype=torch.uint8, device=occ0.device)
-    acc_sum = torch.zeros(C, dtype=torch.int64, device=occ0.device)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record(stream)
-    for x in range(rounds):
-        ch.sweep(per, ladder[:, None], per, seed=0)
-        ch.remc_exchange(R, ladder, x, 1, slot, acc)
-        acc_sum += acc
-    b.record(stream)
-    torch.cuda.synchronize()
-    sec = a.elapsed_time(b) * 1e-3
-    _, _, st = ch.export()
-    ch.close()
+    out = {}
+    for mode in ("graph", "eager"):
+        ch = G.Chains(pb, occ0, G.GOAC_MIXED)
+        ch.set_rows(np.tile(np.arange(R), groups))
+        slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
+        acc = torch.zeros(C, dtype=torch.uint8, device=occ0.device)
+        acc_sum = torch.zeros(C, dtype=torch.int64, device=occ0.device)
+        if mode == "graph":
+            out["remc_autotune"] = list(ch.autotune(per, float(ladder[0])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "graph":
+            ch.remc_run(R, ladder, per, rounds, 0, 1, slot)
+        else:
+            for x in range(rounds):
+                ch.sweep(per, ladder[:, None], per, seed=1)
+                ch.remc_exchange(R, ladder, x, 1, slot, acc)
+                acc_sum += acc
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        _, _, st = ch.export()
+        ch.close()
+        print("  [remc %s] %.3f s" % (mode, sec), file=sys.stderr, flush=True)
+        out["remc_%s_trials_per_s" % mode] = C * rounds * per / sec
+        out["remc_%s_time_s" % mode] = sec
+        if mode == "eager":
+            attempts = groups * sum(len(range(x % 2, R - 1, 2)) for x in range(rounds))
+            out["remc_exchange_accept_rate"] = float(acc_sum.sum().item()) / attempts
+            out["remc_trial_accept_rate"] = float(st["accepts"].sum()) / (C * rounds * per)
+            out["remc_best_E_min"] = float(st["best_E"].min())
+    out["remc_trials_per_s"] = out["remc_graph_trials_per_s"]
     pb.close()
-    print("  [remc] %.3f s" % sec, file=sys.stderr, flush=True)
-    attempts = groups * sum(len(range(x % 2, R - 1, 2)) for x in range(rounds))
-    return {"remc_trials_per_s": C * rounds * per / sec, "remc_time_s": sec,
-            "remc_exchange_accept_rate": float(acc_sum.sum().item()) / attempts,
-            "remc_trial_accept_rate": float(st["accepts"].sum()) / (C * rounds * per),
-            "remc_best_E_min": float(st["best_E"].min())}
+    return out
 
 
 def hybrid(ctx, G, S, torch, stream):

@@ -233,6 +233,18 @@ typedef struct {
     int32_t row;         /* temperature row                                     */
 } goac_chain_stats;
 
+/* Launch autotuning: times a probe sweep of probe_trials trials at temperature kT
+ * for each launch configuration (64 or 256 threads per chain, all or half of the
+ * chains that fit a compute unit's LDS resident at once) and keeps the fastest
+ * for later sweeps whose params.variant is 0. The chains' state is saved before
+ * and restored after the probes, so they are left exactly as they were; results
+ * of later sweeps do not depend on the configuration. Synchronises; allocates a
+ * copy of the chain state for the duration of the call.
+ *   wg_out, per_cu_out : the chosen threads per chain and chains per compute unit
+ *                        (may be NULL) */
+goac_status goac_chains_autotune(goac_chains* ch, uint64_t probe_trials, double kT, int32_t* wg_out,
+                                 int32_t* per_cu_out);
+
 /* Copy chain results to caller buffers (any pointer may be NULL):
  *   occ_dev, best_occ_dev : C x n; stats_dev : C goac_chain_stats (device). */
 goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_occ_dev,
@@ -252,6 +264,19 @@ goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_
  * Sweeps after an exchange run chain c at row = its temperature index. */
 goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host, uint64_t x,
                                uint64_t seed, int32_t* slot_dev, uint8_t* acc_dev);
+
+/* `rounds` replica-exchange rounds, each `trials` trials per chain at the ladder
+ * temperature of its slot followed by exchange step x0 + r (r = 0 .. rounds-1);
+ * the same as alternating goac_mc_sweep (the ladder as an R x 1 table) and
+ * goac_remc_exchange, bit for bit. The chains' rows are set from slot_dev first.
+ * One round (the sweep's kernels and the exchange) is captured once as a HIP
+ * graph and replayed, the step index read from device memory; cells whose MIXED
+ * field re-anchors between sweep chunks (more than 1024 mobile positions) run the
+ * same rounds without capture.
+ *   flags : 0 or GOAC_MC_TRACE_HASH;  reanchor_every : as in goac_mc_params
+ *   slot_dev : groups x R int32 (in/out). Synchronises. */
+goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials, uint64_t rounds,
+                          uint64_t x0, uint64_t seed, uint32_t flags, int32_t reanchor_every, int32_t* slot_dev);
 
 /* ---------------------------------------------------------------- GA (a6) */
 

@@ -71,7 +71,7 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_energies", "goac_topk_fp64", "goac_chains_create", "goac_chains_destroy",
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
             "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
-            "goac_hybrid_round"]
+            "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run"]
 
 
 def load():
@@ -106,6 +106,8 @@ def load():
         "goac_gd_run": ([P, I64, P, I64, C.c_double, P, P], I32),
         "goac_chains_load": ([P, P], I32),
         "goac_hybrid_round": ([P, P, I64, P, P, P], I32),
+        "goac_chains_autotune": ([P, U64, C.c_double, P, P], I32),
+        "goac_remc_run": ([P, I32, P, U64, U64, U64, U64, U32, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -310,6 +312,20 @@ class Chains:
         kT = _np(kT_ladder, np.float64)
         self.ctx.check(load().goac_remc_exchange(self._h, R, kT.ctypes.data_as(C.c_void_p), x, seed,
                                                  _ptr(slot), _ptr(acc)))
+
+    def remc_run(self, R, kT_ladder, trials, rounds, x0, seed, slot, trace=False, reanchor_every=1024):
+        """`rounds` replica-exchange rounds (sweep + exchange step x0 + r), replayed
+        from one captured round; slot is updated in place."""
+        kT = _np(kT_ladder, np.float64)
+        self.ctx.check(load().goac_remc_run(self._h, R, kT.ctypes.data_as(C.c_void_p), trials, rounds, x0, seed,
+                                            TRACE_HASH if trace else 0, reanchor_every, _ptr(slot)))
+
+    def autotune(self, probe_trials=2000, kT=0.05):
+        """Pick the fastest launch configuration on a probe sweep (state unchanged);
+        returns (threads per chain, chains per compute unit)."""
+        wg, pc = C.c_int32(0), C.c_int32(0)
+        self.ctx.check(load().goac_chains_autotune(self._h, probe_trials, kT, C.byref(wg), C.byref(pc)))
+        return wg.value, pc.value
 
     def load(self, occ):
         """Continue every chain from new occupations (counters and rows kept)."""

@@ -19,6 +19,9 @@ __global__ void k_ga_child(int64_t, int32_t, int32_t, int32_t, const int32_t*, c
                            const uint8_t*, const uint64_t*, const int32_t*, int32_t, uint64_t, uint32_t, double,
                            uint8_t*);
 goac_status anchor_batched(goac_ctx*, goac_chains*, int, uint32_t);
+// rows of every group from its slot permutation (hybrid.hip)
+__global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __restrict__ slot,
+                                 ChainScalars* __restrict__ sc);
 constexpr int kInlineAnchorMaxMp = 1024;
 
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
@@ -357,10 +360,13 @@ __global__ void k_export(int64_t n, int32_t M, const int32_t* __restrict__ mob, 
 }
 
 // replica exchange: one thread per group of R consecutive chains
-__global__ void k_remc(int64_t n_groups, int32_t R, const double* __restrict__ kT, uint64_t x, uint64_t seed,
-                       ChainScalars* __restrict__ sc, int32_t* __restrict__ slot, uint8_t* __restrict__ acc) {
+// x_dev, when given, holds the exchange step index (a captured round reads it)
+__global__ void k_remc(int64_t n_groups, int32_t R, const double* __restrict__ kT, uint64_t x,
+                       const uint64_t* __restrict__ x_dev, uint64_t seed, ChainScalars* __restrict__ sc,
+                       int32_t* __restrict__ slot, uint8_t* __restrict__ acc) {
     const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gidx >= n_groups) return;
+    if (x_dev) x = *x_dev;
     int32_t* sl = slot + gidx * R;
     if (acc)
         for (int k = 0; k < R; ++k) acc[gidx * R + k] = 0;
@@ -386,6 +392,9 @@ __global__ void k_set_rows(int64_t C, const int32_t* __restrict__ rows, ChainSca
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < C) sc[c].row = rows[c];
 }
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
+__global__ void k_inc_u64(uint64_t* p) { *p += 1; }
 
 __global__ void k_zero_i32(int32_t* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -918,6 +927,7 @@ static void chains_free(goac_chains* ch) {
     if (ch->arena) (void)hipFree(ch->arena);
     if (ch->kT) (void)hipFree(ch->kT);
     if (ch->scratch) (void)hipFree(ch->scratch);
+    if (ch->ladder) (void)hipFree(ch->ladder);
 }
 
 extern "C" goac_status goac_chains_load(goac_chains* ch, const uint8_t* occ_dev) {
@@ -1028,40 +1038,34 @@ extern "C" goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows
     return GOAC_OK;
 }
 
-extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm) {
-    if (!ch) return GOAC_EINVAL;
+// ------------------------------------------------------------------ sweep planning
+// The launch configuration of a sweep: threads per chain (wg), chains resident per
+// compute unit (per_cu, bounded by the LDS a chain needs) and the grid.
+struct SweepPlan {
+    int wg = 64;
+    int per_cu = 1;
+    int grid = 1;
+    size_t lds = 0;
+    McArgs a{};
+};
+
+static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg_req, int per_cu_req,
+                              SweepPlan* out) {
     goac_ctx* ctx = ch->ctx;
-    if (!prm || !prm->kT_host || prm->n_rows <= 0 || prm->n_blocks <= 0 || prm->block_len == 0)
-        return fail(ctx, GOAC_EINVAL, "mc_sweep: bad parameters");
-    if (prm->n_rows <= ch->max_row) return fail(ctx, GOAC_EINVAL, "mc_sweep: a chain's temperature row is beyond n_rows");
-    const size_t nkT = (size_t)prm->n_rows * prm->n_blocks;
-    for (size_t x = 0; x < nkT; ++x)
-        if (!(prm->kT_host[x] > 0.0)) return fail(ctx, GOAC_EINVAL, "mc_sweep: kT must be positive");
     const bool mixed = ch->prec == GOAC_MIXED;
-    if (mixed && prm->reanchor_every <= 0) return fail(ctx, GOAC_EINVAL, "mc_sweep: reanchor_every must be positive");
-    if (prm->n_trials == 0) return GOAC_OK;
-    GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    if (nkT > ch->kT_cap) {
-        if (ch->kT) {
-            GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            GOAC_HIP(ctx, hipFree(ch->kT));
-            ch->kT = nullptr;
-        }
-        GOAC_TRY(dalloc(ctx, &ch->kT, nkT));
-        ch->kT_cap = nkT;
-    }
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->kT, prm->kT_host, nkT * 8, hipMemcpyHostToDevice, ctx->stream));
-    // the persistent grid pulls chains from a counter that starts at zero (reset before each launch)
-    const int wg = prm->variant == 64 || prm->variant == 256 ? prm->variant : (ch->max_Mp >= 2048 ? 256 : 64);
-    if (prm->variant != 0 && prm->variant != 64 && prm->variant != 256)
-        return fail(ctx, GOAC_EINVAL, "mc_sweep: variant must be 0, 64 or 256");
+    int wg = wg_req == 64 || wg_req == 256 ? wg_req : (ch->max_Mp >= 2048 ? 256 : 64);
     const size_t phi_bytes = (size_t)round_up(ch->max_Mp * (mixed ? 4 : 8), 16);
     const size_t lds = phi_bytes + (size_t)ch->max_Mp * (1 + 1 + 2 + 2) + round_up(ch->max_tab * 4, 16) +
                        kMaxSpecies * 8;
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "mc_sweep: the chain state does not fit in LDS");
-    const int per_cu = std::max<int>(1, std::min<int>(wg == 64 ? 16 : 4, (int)((160 * 1024) / lds)));
-    int grid = std::min<int64_t>(ch->C, (int64_t)ctx->num_cus * per_cu);
-    McArgs a;
+    const int cap = std::max<int>(1, std::min<int>(wg == 64 ? 16 : 4, (int)((160 * 1024) / lds)));
+    const int per_cu = per_cu_req > 0 ? std::min(per_cu_req, cap) : cap;
+    SweepPlan& P = *out;
+    P.wg = wg;
+    P.per_cu = per_cu;
+    P.lds = lds;
+    P.grid = (int)std::min<int64_t>(ch->C, (int64_t)ctx->num_cus * per_cu);
+    McArgs& a = P.a;
     a.insts = ch->insts;
     a.sc = ch->sc;
     a.phi = ch->phi;
@@ -1080,22 +1084,164 @@ extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm)
     a.lds_phi_bytes = (int32_t)phi_bytes;
     a.Mp_max = ch->max_Mp;
     a.tab_max = (int32_t)round_up(ch->max_tab, 4);
-    const bool trace = (prm->flags & GOAC_MC_TRACE_HASH) != 0;
     // MIXED: small cells re-anchor inside the kernel; large cells run in chunks of
     // 8 x reanchor_every trials with a batched FP64 anchor of the due chains after each
     a.inline_anchor = (mixed && ch->max_Mp > kInlineAnchorMaxMp) ? 0 : 1;
     a.pad_ = 0;
-    if (a.inline_anchor) {
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
-        return mc_launch(ctx, a, mixed, trace, wg, lds, grid);
+    return GOAC_OK;
+}
+
+// device kT table of a sweep (rows x blocks), copied from the host unless it equals
+// the table uploaded last (a copy from pageable host memory waits for the stream)
+static goac_status sweep_upload_kT(goac_chains* ch, const double* kT_host, size_t nkT) {
+    goac_ctx* ctx = ch->ctx;
+    if (ch->kT && ch->kT_last.size() == nkT && std::equal(ch->kT_last.begin(), ch->kT_last.end(), kT_host))
+        return GOAC_OK;
+    ch->kT_last.assign(kT_host, kT_host + nkT);
+    if (nkT > ch->kT_cap) {
+        if (ch->kT) {
+            GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            GOAC_HIP(ctx, hipFree(ch->kT));
+            ch->kT = nullptr;
+        }
+        GOAC_TRY(dalloc(ctx, &ch->kT, nkT));
+        ch->kT_cap = nkT;
     }
-    const uint64_t chunk = (uint64_t)prm->reanchor_every * 8;
-    for (uint64_t done = 0; done < prm->n_trials; done += chunk) {
-        a.n_trials = std::min<uint64_t>(chunk, prm->n_trials - done);
+    GOAC_HIP(ctx, hipMemcpyAsync(ch->kT, kT_host, nkT * 8, hipMemcpyHostToDevice, ctx->stream));
+    return GOAC_OK;
+}
+
+// the launches of a sweep: kernels only (no host copies), so a stream capture may
+// record them. The persistent grid pulls chains from a counter reset before each
+// launch.
+static goac_status sweep_enqueue(goac_chains* ch, SweepPlan P, bool trace, uint64_t n_trials,
+                                 int32_t reanchor_every) {
+    goac_ctx* ctx = ch->ctx;
+    const bool mixed = ch->prec == GOAC_MIXED;
+    P.a.kT = ch->kT;
+    if (P.a.inline_anchor) {
+        P.a.n_trials = n_trials;
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
-        GOAC_TRY(mc_launch(ctx, a, mixed, trace, wg, lds, grid));
-        for (size_t i = 0; i < ch->pbs.size(); ++i) GOAC_TRY(anchor_batched(ctx, ch, (int)i, (uint32_t)prm->reanchor_every));
+        return mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid);
     }
+    const uint64_t chunk = (uint64_t)reanchor_every * 8;
+    for (uint64_t done = 0; done < n_trials; done += chunk) {
+        P.a.n_trials = std::min<uint64_t>(chunk, n_trials - done);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+        GOAC_TRY(mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid));
+        for (size_t i = 0; i < ch->pbs.size(); ++i)
+            GOAC_TRY(anchor_batched(ctx, ch, (int)i, (uint32_t)reanchor_every));
+    }
+    return GOAC_OK;
+}
+
+static goac_status sweep_check(goac_chains* ch, const goac_mc_params* prm) {
+    goac_ctx* ctx = ch->ctx;
+    if (!prm || !prm->kT_host || prm->n_rows <= 0 || prm->n_blocks <= 0 || prm->block_len == 0)
+        return fail(ctx, GOAC_EINVAL, "mc_sweep: bad parameters");
+    if (prm->n_rows <= ch->max_row) return fail(ctx, GOAC_EINVAL, "mc_sweep: a chain's temperature row is beyond n_rows");
+    const size_t nkT = (size_t)prm->n_rows * prm->n_blocks;
+    for (size_t x = 0; x < nkT; ++x)
+        if (!(prm->kT_host[x] > 0.0)) return fail(ctx, GOAC_EINVAL, "mc_sweep: kT must be positive");
+    if (ch->prec == GOAC_MIXED && prm->reanchor_every <= 0)
+        return fail(ctx, GOAC_EINVAL, "mc_sweep: reanchor_every must be positive");
+    if (prm->variant != 0 && prm->variant != 64 && prm->variant != 256)
+        return fail(ctx, GOAC_EINVAL, "mc_sweep: variant must be 0, 64 or 256");
+    return GOAC_OK;
+}
+
+extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    GOAC_TRY(sweep_check(ch, prm));
+    if (prm->n_trials == 0) return GOAC_OK;
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(sweep_upload_kT(ch, prm->kT_host, (size_t)prm->n_rows * prm->n_blocks));
+    SweepPlan P;
+    // an explicit variant wins; otherwise the tuned configuration, else the size rule
+    const int wg = prm->variant != 0 ? prm->variant : ch->tuned_wg;
+    const int per_cu = prm->variant != 0 ? 0 : ch->tuned_per_cu;
+    GOAC_TRY(sweep_plan(ch, prm, wg, per_cu, &P));
+    return sweep_enqueue(ch, P, (prm->flags & GOAC_MC_TRACE_HASH) != 0, prm->n_trials, prm->reanchor_every);
+}
+
+// ------------------------------------------------------------------ autotuning
+// Times short probe sweeps of each launch configuration on the chains themselves
+// and keeps the fastest for later sweeps that request no variant. The chain state
+// (scalars, field, occupations, position lists, best copies) is saved before and
+// restored after every probe, so the chains are left exactly as they were.
+extern "C" goac_status goac_chains_autotune(goac_chains* ch, uint64_t probe_trials, double kT, int32_t* wg_out,
+                                            int32_t* per_cu_out) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    if (probe_trials == 0 || !(kT > 0.0)) return fail(ctx, GOAC_EINVAL, "chains_autotune: bad arguments");
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = ctx->stream;
+    const bool mixed = ch->prec == GOAC_MIXED;
+    const size_t b_sc = ch->C * sizeof(ChainScalars), b_phi = ch->total * (mixed ? 4 : 8);
+    const size_t b_occ = ch->total, b_perm = ch->total * 2, b_best = ch->total;
+    const size_t parts[5] = {b_sc, b_phi, b_occ, b_perm, b_best};
+    void* const srcs[5] = {ch->sc, ch->phi, ch->occ, ch->perm, ch->best};
+    size_t offs[5], tot = 0;
+    for (int q = 0; q < 5; ++q) { offs[q] = tot; tot += round_up(parts[q], 256); }
+    char* save = nullptr;
+    GOAC_HIP(ctx, hipMalloc((void**)&save, tot));
+    auto copy_all = [&](bool to_save) -> goac_status {
+        for (int q = 0; q < 5; ++q) {
+            char* s = to_save ? (char*)srcs[q] : save + offs[q];
+            char* d = to_save ? save + offs[q] : (char*)srcs[q];
+            GOAC_HIP(ctx, hipMemcpyAsync(d, s, parts[q], hipMemcpyDeviceToDevice, sm));
+        }
+        return GOAC_OK;
+    };
+    goac_status st = copy_all(true);
+    std::vector<double> table((size_t)ch->max_row + 1, kT);
+    goac_mc_params prm{};
+    prm.seed = 0x5eed;
+    prm.n_trials = probe_trials;
+    prm.kT_host = table.data();
+    prm.n_rows = (int32_t)table.size();
+    prm.n_blocks = 1;
+    prm.block_len = probe_trials;
+    prm.reanchor_every = 1024;
+    if (st == GOAC_OK) st = sweep_upload_kT(ch, table.data(), table.size());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == GOAC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(ctx, GOAC_EHIP, "chains_autotune: event creation failed");
+    float best_ms = INFINITY;
+    int best_wg = 0, best_pc = 0;
+    for (int wg : {64, 256}) {
+        if (st != GOAC_OK) break;
+        SweepPlan P0;
+        if ((st = sweep_plan(ch, &prm, wg, 0, &P0)) != GOAC_OK) break;
+        const int cap = P0.per_cu;
+        std::vector<int> cands = {cap};
+        if (cap / 2 >= 1) cands.push_back(cap / 2);
+        for (int pc : cands) {
+            SweepPlan P;
+            if ((st = sweep_plan(ch, &prm, wg, pc, &P)) != GOAC_OK) break;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && st == GOAC_OK; ++rep) {   // the first run warms the caches
+                if ((st = copy_all(false)) != GOAC_OK) break;
+                if (hipEventRecord(e0, sm) != hipSuccess) { st = fail(ctx, GOAC_EHIP, "event"); break; }
+                if ((st = sweep_enqueue(ch, P, false, probe_trials, prm.reanchor_every)) != GOAC_OK) break;
+                if (hipEventRecord(e1, sm) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    st = fail(ctx, GOAC_EHIP, "chains_autotune: timing failed");
+            }
+            if (st == GOAC_OK && ms < best_ms) { best_ms = ms; best_wg = wg; best_pc = pc; }
+        }
+    }
+    if (st == GOAC_OK) st = copy_all(false);
+    (void)hipStreamSynchronize(sm);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    if (st != GOAC_OK) return st;
+    ch->tuned_wg = best_wg;
+    ch->tuned_per_cu = best_pc;
+    if (wg_out) *wg_out = best_wg;
+    if (per_cu_out) *per_cu_out = best_pc;
     return GOAC_OK;
 }
 
@@ -1129,14 +1275,106 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
     for (int k = 0; k < R; ++k)
         if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_exchange: kT must be positive");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    void* ws = nullptr;
-    GOAC_TRY(workspace(ctx, 0, (size_t)R * 8, &ws));
-    double* d = (double*)ws;
-    GOAC_HIP(ctx, hipMemcpyAsync(d, kT_host, R * 8, hipMemcpyHostToDevice, ctx->stream));
+    // the ladder lives with the chains; copied only when it changed
+    if (!ch->ladder || ch->ladder_last.size() != (size_t)R ||
+        !std::equal(ch->ladder_last.begin(), ch->ladder_last.end(), kT_host)) {
+        if ((size_t)R > ch->ladder_cap) {
+            if (ch->ladder) {
+                GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                GOAC_HIP(ctx, hipFree(ch->ladder));
+                ch->ladder = nullptr;
+            }
+            GOAC_TRY(dalloc(ctx, &ch->ladder, (size_t)R));
+            ch->ladder_cap = (size_t)R;
+        }
+        ch->ladder_last.assign(kT_host, kT_host + R);
+        GOAC_HIP(ctx, hipMemcpyAsync(ch->ladder, kT_host, R * 8, hipMemcpyHostToDevice, ctx->stream));
+    }
+    const double* d = ch->ladder;
     const int64_t ng = ch->C / R;
-    hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, ctx->stream, ng, R, d, x, seed, ch->sc,
-                       slot, acc);
+    hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, ctx->stream, ng, R, d, x,
+                       (const uint64_t*)nullptr, seed, ch->sc, slot, acc);
     GOAC_CHECK_LAUNCH(ctx);
     ch->max_row = std::max(ch->max_row, R - 1);
+    return GOAC_OK;
+}
+
+
+// Many replica-exchange rounds: the sweep of one round and its exchange step are
+// captured once as a graph and replayed, the step index x0 + r read from device
+// memory. Cells whose MIXED field re-anchors between sweep chunks (workspace sized
+// on the host) run the same rounds without capture.
+extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials,
+                                     uint64_t rounds, uint64_t x0, uint64_t seed, uint32_t flags,
+                                     int32_t reanchor_every, int32_t* slot) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    if (R < 2 || !kT_host || !slot || ch->C % R != 0 || trials == 0 || (flags & ~GOAC_MC_TRACE_HASH))
+        return fail(ctx, GOAC_EINVAL, "remc_run: bad arguments");
+    for (int k = 0; k < R; ++k)
+        if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_run: kT must be positive");
+    if (ch->prec == GOAC_MIXED && reanchor_every <= 0) return fail(ctx, GOAC_EINVAL, "remc_run: reanchor_every");
+    if (rounds == 0) return GOAC_OK;
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = ctx->stream;
+    const int64_t ng = ch->C / R;
+    goac_mc_params prm{};
+    prm.seed = seed;
+    prm.n_trials = trials;
+    prm.kT_host = kT_host;
+    prm.n_rows = R;
+    prm.n_blocks = 1;
+    prm.block_len = trials;
+    prm.reanchor_every = reanchor_every > 0 ? reanchor_every : 1024;
+    prm.flags = flags;
+    // the ladder is the sweep's table (R rows x 1 block) and the exchange's
+    GOAC_TRY(sweep_upload_kT(ch, kT_host, (size_t)R));
+    SweepPlan P;
+    GOAC_TRY(sweep_plan(ch, &prm, ch->tuned_wg, ch->tuned_per_cu, &P));
+    const bool trace = (flags & GOAC_MC_TRACE_HASH) != 0;
+    ch->max_row = std::max(ch->max_row, R - 1);
+    hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, sm, ng, R, slot, ch->sc);
+    GOAC_CHECK_LAUNCH(ctx);
+    if (!P.a.inline_anchor) {
+        for (uint64_t r = 0; r < rounds; ++r) {
+            GOAC_TRY(sweep_enqueue(ch, P, trace, trials, prm.reanchor_every));
+            hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, sm, ng, R, ch->kT, x0 + r,
+                               (const uint64_t*)nullptr, seed, ch->sc, slot, (uint8_t*)nullptr);
+            GOAC_CHECK_LAUNCH(ctx);
+        }
+        return GOAC_OK;
+    }
+    void* xs = nullptr;
+    GOAC_TRY(workspace(ctx, 2, 256, &xs));
+    uint64_t* xdev = (uint64_t*)xs;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, sm, xdev, x0);
+    GOAC_CHECK_LAUNCH(ctx);
+    // capture on a private stream (the context's may be the null stream, which
+    // cannot be captured); the graph then runs on the context's stream
+    hipStream_t cap = nullptr;
+    GOAC_HIP(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ctx->stream = cap;
+    goac_status st = GOAC_OK;
+    hipError_t ec = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (ec == hipSuccess) {
+        st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every);
+        if (st == GOAC_OK) {
+            hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cap, ng, R, ch->kT,
+                               (uint64_t)0, (const uint64_t*)xdev, seed, ch->sc, slot, (uint8_t*)nullptr);
+            hipLaunchKernelGGL(k_inc_u64, dim3(1), dim3(1), 0, cap, xdev);
+        }
+        ec = hipStreamEndCapture(cap, &graph);
+    }
+    ctx->stream = sm;
+    if (st == GOAC_OK && ec == hipSuccess) ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (uint64_t r = 0; st == GOAC_OK && ec == hipSuccess && r < rounds; ++r) ec = hipGraphLaunch(exec, sm);
+    if (st == GOAC_OK && ec == hipSuccess) ec = hipStreamSynchronize(sm);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (st != GOAC_OK) return st;
+    if (ec != hipSuccess) return fail(ctx, GOAC_EHIP, std::string("remc_run: graph: ") + hipGetErrorString(ec));
     return GOAC_OK;
 }

@@ -217,6 +217,12 @@ struct goac_chains {
     std::vector<int64_t> occ_row_off; // byte offset of an instance's first occupation row
     void* scratch = nullptr;          // hybrid rounds: candidate rows, energies, ranks (grown on demand)
     size_t scratch_size = 0;
+    int32_t tuned_wg = 0;             // launch configuration chosen by goac_chains_autotune (0: size rule)
+    int32_t tuned_per_cu = 0;
+    std::vector<double> kT_last;      // the kT table held in kT (uploads are skipped when unchanged)
+    double* ladder = nullptr;         // replica-exchange ladder (device) and its host copy
+    size_t ladder_cap = 0;
+    std::vector<double> ladder_last;
 };
 
 // ------------------------------------------------------------------ error helpers

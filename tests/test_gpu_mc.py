@@ -255,6 +255,58 @@ def test_remc_exchange_bitexact(ctx, cfg1):
         assert np.array_equal(ref_slot[g][rows[g]], np.arange(R))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_leaves_chains_unchanged(ctx, cfg2, prec):
+    """The tuner's probe sweeps leave the chains as they were, and sweeps with the
+    chosen configuration stay bit-exact against the oracle."""
+    cell, V = cfg2
+    kT = np.geomspace(0.5, 0.01, 20)
+    occ0 = O.init_occupations(cell, 48, seed=7)
+    st = _run_oracle(cell, V, occ0, 20000, kT, 1000, 7)
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    ch = G.Chains(pb, torch.from_numpy(occ0), prec)
+    wg, pc = ch.autotune(2000, 0.05)
+    assert wg in (64, 256) and pc >= 1
+    occ, best, stats = ch.export()
+    assert np.array_equal(occ.cpu().numpy(), occ0) and np.all(stats["t"] == 0) and np.all(stats["accepts"] == 0)
+    ch.sweep(20000, kT, 1000, seed=7, trace=True)
+    occ, best, stats = ch.export()
+    _compare(cell, stats, occ.cpu().numpy(), best.cpu().numpy(), st, prec, V)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec):
+    """Rounds replayed from one captured graph equal the same rounds launched one
+    by one (sweep + exchange), bit for bit; checked after several replays, after a
+    second call that captures again, and with eager work and synchronisation
+    between the calls."""
+    cell, V = cfg2
+    R, groups = 4, 16
+    ladder = np.array([0.05, 0.1, 0.2, 0.4])
+    occ0 = O.init_occupations(cell, R * groups, seed=12)
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    a = G.Chains(pb, torch.from_numpy(occ0), prec)
+    b = G.Chains(pb, torch.from_numpy(occ0), prec)
+    sa = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device="cuda")
+    sb = sa.clone()
+    b.set_rows(np.tile(np.arange(R), groups))
+    x = 0
+    for rounds in (3, 1, 4):
+        a.remc_run(R, ladder, 700, rounds, x, 5, sa, trace=True)
+        for r in range(rounds):
+            b.sweep(700, ladder[:, None], 700, seed=5, trace=True)
+            b.remc_exchange(R, ladder, x + r, 5, sb)
+        x += rounds
+        oa, ba, st_a = a.export()
+        ob, bb, st_b = b.export()
+        assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+        assert np.array_equal(oa.cpu().numpy(), ob.cpu().numpy())
+        for f in ("t", "hash", "accepts", "updates", "E", "best_E", "row"):
+            assert np.array_equal(st_a[f], st_b[f]), f
+        pb.energies(oa, 0)                        # eager work between the calls
+        torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ GA
 
 @pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96),
