@@ -24,6 +24,43 @@ __global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __r
                                  ChainScalars* __restrict__ sc);
 constexpr int kInlineAnchorMaxMp = 1024;
 
+// All work of a context runs on its one stream, so a released block is reused only
+// by work queued after everything that used it. The cache keeps at most
+// kPoolMaxBytes; beyond that released blocks are freed.
+constexpr size_t kPoolMaxBytes = (size_t)8 << 30;
+
+goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out) {
+    const size_t want = (size_t)round_up((int64_t)*bytes, (int64_t)1 << 16);
+    auto it = ctx->pool.lower_bound(want);
+    if (it != ctx->pool.end() && it->first <= 2 * want) {
+        *out = it->second;
+        *bytes = it->first;
+        ctx->pool_bytes -= it->first;
+        ctx->pool.erase(it);
+        return GOAC_OK;
+    }
+    if (hipMalloc(out, want) != hipSuccess) {
+        // release the cache and try once more
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& b : ctx->pool) (void)hipFree(b.second);
+        ctx->pool.clear();
+        ctx->pool_bytes = 0;
+        if (hipMalloc(out, want) != hipSuccess) return fail(ctx, GOAC_ENOMEM, "device allocation failed");
+    }
+    *bytes = want;
+    return GOAC_OK;
+}
+
+void pool_put(goac_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    if (ctx->pool_bytes + bytes > kPoolMaxBytes) {
+        (void)hipFree(p);
+        return;
+    }
+    ctx->pool.emplace(bytes, p);
+    ctx->pool_bytes += bytes;
+}
+
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
     if (slot < 0 || slot >= kWsSlots) return fail(ctx, GOAC_EINVAL, "workspace slot");
     if (bytes > ctx->ws_size[slot]) {
@@ -442,7 +479,7 @@ struct ArenaPlan {
 };
 
 void problem_free(goac_problem* pb) {
-    if (pb->arena) (void)hipFree(pb->arena);
+    if (pb->arena) pool_put(pb->ctx, pb->arena, pb->arena_bytes);
     pb->arena = nullptr;
 }
 
@@ -469,6 +506,7 @@ extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int q = 0; q < kWsSlots; ++q)
         if (ctx->ws[q]) (void)hipFree(ctx->ws[q]);
+    for (auto& b : ctx->pool) (void)hipFree(b.second);
     delete ctx;
 }
 
@@ -610,7 +648,8 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
                  o_rmax = ap.take(M * 4), o_rabs = ap.take(M * 8), o_h = ap.take(Mp * 8), o_ht = ap.take(Mp * 8),
                  o_pbar = ap.take(kMaxSub * 8), o_efix = ap.take((nf + 1) * 8), o_vc = ap.take(Mp * 8),
                  o_phi = ap.take(Mp * 8), o_out = ap.take(64);
-    if (hipMalloc(&pb->arena, ap.end) != hipSuccess) {
+    pb->arena_bytes = ap.end;
+    if (pool_get(ctx, &pb->arena_bytes, &pb->arena) != GOAC_OK) {
         ctx->err = "problem_create: device allocation failed";
         return bail(GOAC_ENOMEM);
     }
@@ -689,9 +728,10 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     return GOAC_OK;
 }
 
+// Destruction does not wait for the stream: the arena returns to the context's
+// cache, whose blocks only work queued later on the same stream reuses.
 extern "C" void goac_problem_destroy(goac_problem* pb) {
     if (!pb) return;
-    (void)hipStreamSynchronize(pb->ctx->stream);
     problem_free(pb);
     delete pb;
 }
@@ -832,7 +872,8 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     const size_t o_perm = ap.take(tot * sizeof(uint16_t));
     const size_t o_best = ap.take(tot);
     const size_t o_phi = ap.take(tot * (mixed ? 4 : 8));
-    GOAC_HIP(ctx, hipMalloc(&ch->arena, ap.end));
+    ch->arena_bytes = ap.end;
+    GOAC_TRY(pool_get(ctx, &ch->arena_bytes, &ch->arena));
     char* base = (char*)ch->arena;
     ch->sc = (ChainScalars*)(base + o_sc);
     ch->insts = (McInst*)(base + o_in);
@@ -924,10 +965,14 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
 }
 
 static void chains_free(goac_chains* ch) {
-    if (ch->arena) (void)hipFree(ch->arena);
-    if (ch->kT) (void)hipFree(ch->kT);
-    if (ch->scratch) (void)hipFree(ch->scratch);
-    if (ch->ladder) (void)hipFree(ch->ladder);
+    if (ch->arena) pool_put(ch->ctx, ch->arena, ch->arena_bytes);
+    ch->arena = nullptr;
+    pool_put(ch->ctx, ch->kT, ch->kT_cap * 8);
+    pool_put(ch->ctx, ch->scratch, ch->scratch_size);
+    pool_put(ch->ctx, ch->ladder, ch->ladder_cap * 8);
+    ch->kT = nullptr;
+    ch->scratch = nullptr;
+    ch->ladder = nullptr;
 }
 
 extern "C" goac_status goac_chains_load(goac_chains* ch, const uint8_t* occ_dev) {
@@ -1015,7 +1060,6 @@ extern "C" goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_
 
 extern "C" void goac_chains_destroy(goac_chains* ch) {
     if (!ch) return;
-    (void)hipStreamSynchronize(ch->ctx->stream);
     chains_free(ch);
     delete ch;
 }
@@ -1026,13 +1070,12 @@ extern "C" goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows
     if (!rows) return fail(ctx, GOAC_EINVAL, "chains_set_rows: null rows");
     for (int64_t c = 0; c < ch->C; ++c)
         if (rows[c] < 0) return fail(ctx, GOAC_EINVAL, "chains_set_rows: negative row");
-    int32_t* d = nullptr;
-    GOAC_HIP(ctx, hipMallocAsync((void**)&d, ch->C * 4, ctx->stream));
+    void* ws = nullptr;
+    GOAC_TRY(workspace(ctx, 0, (size_t)ch->C * 4, &ws));
+    int32_t* d = (int32_t*)ws;
     GOAC_HIP(ctx, hipMemcpyAsync(d, rows, ch->C * 4, hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((ch->C + 255) / 256)), dim3(256), 0, ctx->stream, ch->C, d, ch->sc);
     GOAC_CHECK_LAUNCH(ctx);
-    GOAC_HIP(ctx, hipFreeAsync(d, ctx->stream));
-    GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ch->max_row = 0;
     for (int64_t c = 0; c < ch->C; ++c) ch->max_row = std::max(ch->max_row, rows[c]);
     return GOAC_OK;
@@ -1099,13 +1142,14 @@ static goac_status sweep_upload_kT(goac_chains* ch, const double* kT_host, size_
         return GOAC_OK;
     ch->kT_last.assign(kT_host, kT_host + nkT);
     if (nkT > ch->kT_cap) {
-        if (ch->kT) {
-            GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            GOAC_HIP(ctx, hipFree(ch->kT));
-            ch->kT = nullptr;
-        }
-        GOAC_TRY(dalloc(ctx, &ch->kT, nkT));
-        ch->kT_cap = nkT;
+        pool_put(ctx, ch->kT, ch->kT_cap * 8);
+        ch->kT = nullptr;
+        ch->kT_cap = 0;
+        size_t bytes = nkT * 8;
+        void* p = nullptr;
+        GOAC_TRY(pool_get(ctx, &bytes, &p));
+        ch->kT = (double*)p;
+        ch->kT_cap = bytes / 8;
     }
     GOAC_HIP(ctx, hipMemcpyAsync(ch->kT, kT_host, nkT * 8, hipMemcpyHostToDevice, ctx->stream));
     return GOAC_OK;
@@ -1279,13 +1323,14 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
     if (!ch->ladder || ch->ladder_last.size() != (size_t)R ||
         !std::equal(ch->ladder_last.begin(), ch->ladder_last.end(), kT_host)) {
         if ((size_t)R > ch->ladder_cap) {
-            if (ch->ladder) {
-                GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-                GOAC_HIP(ctx, hipFree(ch->ladder));
-                ch->ladder = nullptr;
-            }
-            GOAC_TRY(dalloc(ctx, &ch->ladder, (size_t)R));
-            ch->ladder_cap = (size_t)R;
+            pool_put(ctx, ch->ladder, ch->ladder_cap * 8);
+            ch->ladder = nullptr;
+            ch->ladder_cap = 0;
+            size_t bytes = (size_t)R * 8;
+            void* p = nullptr;
+            GOAC_TRY(pool_get(ctx, &bytes, &p));
+            ch->ladder = (double*)p;
+            ch->ladder_cap = bytes / 8;
         }
         ch->ladder_last.assign(kT_host, kT_host + R);
         GOAC_HIP(ctx, hipMemcpyAsync(ch->ladder, kT_host, R * 8, hipMemcpyHostToDevice, ctx->stream));

@@ -8,6 +8,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -170,6 +171,8 @@ struct goac_ctx {
     std::string err;
     void* ws[kWsSlots] = {nullptr, nullptr, nullptr};  // scratch, grown on demand
     size_t ws_size[kWsSlots] = {0, 0, 0};
+    std::multimap<size_t, void*> pool;  // released arenas by size, reused by later ones
+    size_t pool_bytes = 0;
 };
 
 struct goac_problem {
@@ -184,6 +187,7 @@ struct goac_problem {
     int32_t* fixed_idx = nullptr;    // fixed sites
     int32_t n_fixed = 0;
     void* arena = nullptr;           // one allocation holding every device array
+    size_t arena_bytes = 0;
 };
 
 struct goac_chains {
@@ -203,6 +207,7 @@ struct goac_chains {
     int32_t* order = nullptr;         // C, longest chains first
     int32_t* queue = nullptr;         // work counter of the persistent sweep
     void* arena = nullptr;            // one allocation holding every array below
+    size_t arena_bytes = 0;
     double* kT = nullptr;             // device kT table
     size_t kT_cap = 0;
     int64_t* d_offs = nullptr;        // C element offsets (device)
@@ -274,6 +279,11 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
 
 // scratch memory of a context (grown, never shrunk)
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
+
+// arenas of problems and chain sets: a block released to the context is handed to
+// the next arena that fits in it (at most twice its size); *bytes is rounded up
+goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out);
+void pool_put(goac_ctx* ctx, void* p, size_t bytes);
 
 // population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies
 // by (E, index); cnt_scratch holds P int32

@@ -16,6 +16,12 @@
 
 #include "common.h"
 
+#define GOAC_TRY_H(expr)               \
+    do {                               \
+        goac_status s_ = (expr);       \
+        if (s_ != GOAC_OK) return s_;  \
+    } while (0)
+
 namespace goac {
 
 // rows of every group from its slot permutation (a non-permutation is left alone)
@@ -60,14 +66,12 @@ __global__ void k_inject(int64_t n_groups, int32_t R, int32_t n_inj, int64_t n, 
 static goac_status chains_scratch(goac_chains* ch, size_t bytes, void** out) {
     goac_ctx* ctx = ch->ctx;
     if (bytes > ch->scratch_size) {
-        if (ch->scratch) {
-            GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            GOAC_HIP(ctx, hipFree(ch->scratch));
-            ch->scratch = nullptr;
-            ch->scratch_size = 0;
-        }
-        GOAC_HIP(ctx, hipMalloc(&ch->scratch, bytes));
-        ch->scratch_size = bytes;
+        pool_put(ctx, ch->scratch, ch->scratch_size);
+        ch->scratch = nullptr;
+        ch->scratch_size = 0;
+        size_t got = bytes;
+        GOAC_TRY_H(pool_get(ctx, &got, &ch->scratch));
+        ch->scratch_size = got;
     }
     *out = ch->scratch;
     return GOAC_OK;
@@ -77,11 +81,6 @@ static goac_status chains_scratch(goac_chains* ch, size_t bytes, void** out) {
 
 using namespace goac;
 
-#define GOAC_TRY_H(expr)               \
-    do {                               \
-        goac_status s_ = (expr);       \
-        if (s_ != GOAC_OK) return s_;  \
-    } while (0)
 
 extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int64_t P, uint8_t* pop_dev,
                                          double* E_dev, const goac_hybrid_params* prm) {

@@ -241,20 +241,23 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             const int i = (int)mulshift(r.x, (uint32_t)M);
             const int s = S == 1 ? 0 : msub[i];
             const int sa = occ[i];
-            const int na = cnt[s * E + sa];
+            // s < 16, E < 256, positions < 2^16: 24-bit products run at the full
+            // vector rate (32-bit integer products run at a quarter of it)
+            const int se = (int)__umul24((unsigned)s, (unsigned)E) + sa;
+            const int na = cnt[se];
             const int csz = subsize[s] - na;
             int j = i;
             bool stop = false;
             double d = 0.0, dE = 0.0, e = 0.0, L32 = 0.0, m32 = 0.0;
             if (valid && csz > 0) {
                 const int k = (int)mulshift(r.y, (uint32_t)csz);
-                const int idx = k < offs[s * E + sa] ? k : k + na;
+                const int idx = k < offs[se] ? k : k + na;
                 j = perm[suboff[s] + idx];
                 const int sb = occ[j];
                 d = chg[sb] - chg[sa];
                 const double phi_i = (double)phi[i], phi_j = (double)phi[j];
                 const double Vii = diag[i], Vjj = diag[j];
-                const double Vij = V64[(int64_t)i * Mp + j];
+                const double Vij = V64[__umul24((unsigned)i, (unsigned)Mp) + (unsigned)j];
                 dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
                 // Metropolis threshold L = -kT ln u, first in FP32 from the top 24 bits
                 // of u: |L32 - L| <= m32. u32 lies within 2^-25 of u, so its logarithm
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                     // rows i and j streamed as 16-byte vectors, U vectors per thread in
                     // flight before the field is touched
                     constexpr int VEC = MIXED ? 4 : 2;
-                    constexpr int U = WG >= 256 ? 4 : 1;   // one wave per chain: keep registers low
+                    constexpr int U = WG >= 256 ? 8 : 1;   // one wave per chain: keep registers low
                     typedef float f32x4v __attribute__((ext_vector_type(4)));
                     typedef double f64x2v __attribute__((ext_vector_type(2)));
                     using V16 = typename std::conditional<MIXED, f32x4v, f64x2v>::type;
