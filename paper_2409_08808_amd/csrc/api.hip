@@ -809,12 +809,9 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
     if (P > (int64_t)1 << 30) return fail(ctx, GOAC_EINVAL, "ga_generation: population too large");
     const ProblemDev& d = pb->d;
-    // child occupation, path copy and parent B (bytes), then one bit row per species
-    // over the largest sublattice
-    int64_t max_words = 0;
-    for (int s = 0; s < d.S; ++s) max_words = std::max<int64_t>(max_words, (pb->tab_host[2 + s] + 63) / 64);
-    // (at least 16 x 64 words: the register-resident walk builds its rows there)
-    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * std::max<size_t>((size_t)d.E * (size_t)max_words, 16 * 64);
+    // child occupation, path copy and parent B (bytes), then the register walk's
+    // 16 x 64 words of species rows
+    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * 16 * 64;
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "ga_generation: too many mobile positions");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     const int32_t ne = (int32_t)std::min<int64_t>(std::max(prm->n_elite, 0), P);

@@ -127,20 +127,18 @@ __device__ __forceinline__ void wave_lds_order() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Position of the first set bit of a W-word bit row at word index >= w0, where
-// `win` is this lane's word w0 + lane, already loaded (and possibly modified);
-// kInf if the row has none there. Wave-uniform.
-__device__ inline int first_set(uint64_t win, int w0, int W, const uint64_t* row, int lane) {
-    uint64_t m = __ballot(win != 0);
-    while (m == 0) {
-        w0 += 64;
-        if (w0 >= W) return kInf;
-        win = w0 + lane < W ? row[w0 + lane] : 0;
-        m = __ballot(win != 0);
+// first position >= from (in the sublattice's ascending list [0, len)) whose
+// predicate holds, scanning 64 at a time with a ballot; len if none
+template <typename Pred>
+__device__ inline int wave_find(int from, int len, Pred pred) {
+    const int lane = threadIdx.x & 63;
+    for (int base = from; base < len; base += 64) {
+        const int x = base + lane;
+        const bool hit = x < len && pred(x);
+        const uint64_t m = __ballot(hit);
+        if (m) return base + (int)__ffsll((long long)m) - 1;
     }
-    const int l = (int)__ffsll((long long)m) - 1;
-    const uint64_t v = readlane64(win, l);
-    return (w0 + l) * 64 + (int)__ffsll((long long)v) - 1;
+    return len;
 }
 
 // Crossover walk of one sublattice held in registers (len <= 4096 positions,
@@ -154,9 +152,9 @@ __device__ inline int first_set(uint64_t win, int w0, int W, const uint64_t* row
 // it. Returns false on a species id out of range or a broken composition.
 constexpr int kRegSpecies = 16;
 constexpr int kRegMaxLen = 64 * 64;
-// below this length the LDS walk's scans are short and it is the faster one
-// (measured: 256 positions 155 us vs 324 us, 2048 positions 790 us vs 698 us for
-// the 8x8x8 and 4x4x4 rock-salt populations)
+// below this length the scan walk is the faster one (measured per generation:
+// 256 positions 155 us vs 324 us, 2048 positions 830 us vs 698 us, for the 4x4x4
+// and 8x8x8 rock-salt populations)
 constexpr int kRegMinLen = 1024;
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
@@ -309,12 +307,9 @@ __device__ bool crossover_regs(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int 
 //     each swap of the path iff the top bit of Philox(p_mobile, c, g, X) is set.
 //   mutation: with probability p_mut one valid swap, drawn as an MC proposal
 //     with the sublattice's positions ordered by (species, position).
-// The walk keeps, per species e, a bit row of the positions that still disagree
-// with B and hold e in ref, and each row's lowest set bit (lane e of hv). The
-// smallest disagreeing position p is the head of its own species' row, and q is
-// the head of B[p]'s row; a step clears p and q, sets q in the row of the species
-// q now holds unless q then agrees with B, and finds the two new heads with one
-// LDS read per row. The coin bits are drawn for 64 positions at once.
+// Sublattices of 1025..4096 positions with at most 16 species take the
+// register-resident walk (crossover_regs); others the scan walk, which finds p and
+// q with 64-position ballots over the path copy in LDS.
 __global__ __launch_bounds__(64) void k_ga_child(
     int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
     const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob,
@@ -349,7 +344,7 @@ __global__ __launch_bounds__(64) void k_ga_child(
         pb = upper_bound_u64(cum, P, mulhi64(xb, W));
     }
     // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent
-    // B); then the species bit rows of the current sublattice
+    // B); then the register walk's 16 x 64 words of species rows
     const int Mr = (int)round_up(M, 16);
     uint8_t* ch = lds;
     uint8_t* rf = lds + Mr;
@@ -367,7 +362,6 @@ __global__ __launch_bounds__(64) void k_ga_child(
     wave_lds_order();
     for (int s = 0; s < S; ++s) {
         const int base = suboff[s], len = subsize[s];
-        const int Wd = (len + 63) >> 6;
         uint8_t* rs = rf + base;
         uint8_t* cs = ch + base;
         const uint8_t* bs = bb + base;
@@ -375,74 +369,23 @@ __global__ __launch_bounds__(64) void k_ga_child(
             crossover_regs(rs, cs, bs, len, spos + base, mk, (uint32_t)c, g, seed, lane);
             continue;
         }
-        // bit rows: mk[e * Wd + w] bit l <=> position 64 w + l holds e and disagrees with B
-        for (int w = 0; w < Wd; ++w) {
-            const int x = w * 64 + lane;
-            const int rv = x < len ? rs[x] : 255;
-            const bool mis = x < len && rv != bs[x];
-            for (int e = 0; e < E; ++e) {
-                const uint64_t m = __ballot(mis && rv == e);
-                if (lane == 0) mk[e * Wd + w] = m;
+        // scan walk: the next disagreeing position and its partner, 64 positions at a
+        // time; lane 0 swaps the path copy and, on a set coin, the child
+        int p = 0;
+        for (;;) {
+            p = wave_find(p, len, [&](int x) { return rs[x] != bs[x]; });
+            if (p >= len) break;
+            const uint8_t want = bs[p];
+            const int q = wave_find(p + 1, len, [&](int x) { return rs[x] == want && rs[x] != bs[x]; });
+            if (q >= len) break;  // cannot happen: ref and B share the composition
+            if (lane == 0) {
+                const uint8_t t = rs[p]; rs[p] = rs[q]; rs[q] = t;
+                const u32x4 rx = philox((uint32_t)spos[base + p], (uint32_t)c, g, TAG_X, seed);
+                if (rx.x >> 31) { const uint8_t t2 = cs[p]; cs[p] = cs[q]; cs[q] = t2; }
             }
+            wave_lds_order();
+            ++p;
         }
-        wave_lds_order();
-        int hv = kInf;   // lane e: head of species e's row
-        for (int e = 0; e < E; ++e) {
-            const uint64_t v = lane < Wd ? mk[e * Wd + lane] : 0;
-            const int h = first_set(v, 0, Wd, mk + e * Wd, lane);
-            if (lane == e) hv = h;
-        }
-        bool bad = false;
-        for (int w = 0; w < Wd && !bad; ++w) {
-            const int x = w * 64 + lane;
-            const bool in = x < len;
-            int rv = in ? rs[x] : 0;
-            const int bv = in ? bs[x] : 0;
-            uint64_t mm = __ballot(in && rv != bv);
-            if (!mm) continue;
-            bool coin = false;
-            if (in) coin = (philox((uint32_t)spos[base + x], (uint32_t)c, g, TAG_X, seed).x >> 31) != 0;
-            const uint64_t xm = __ballot(coin);
-            while (mm) {
-                const int po = (int)__ffsll((long long)mm) - 1;
-                mm &= mm - 1;
-                const int p = w * 64 + po;
-                const int a = __builtin_amdgcn_readlane(rv, po);
-                const int b = __builtin_amdgcn_readlane(bv, po);
-                if (a >= E || b >= E) { bad = true; break; }         // species id out of range
-                const int q = __builtin_amdgcn_readlane(hv, b);
-                if (q >= len) { bad = true; break; }                 // broken composition
-                const int qw = q >> 6, dq = qw - w;
-                uint64_t* rowb = mk + b * Wd;
-                uint64_t* rowa = mk + a * Wd;
-                uint64_t wb = qw + lane < Wd ? rowb[qw + lane] : 0;
-                uint64_t wa = w + lane < Wd ? rowa[w + lane] : 0;
-                const bool carry = bs[q] != a;   // q keeps disagreeing with B after taking a
-                const uint64_t bitq = 1ull << (q & 63), bitp = 1ull << po;
-                if (lane == 0) { wb &= ~bitq; wa &= ~bitp; }
-                if (carry && dq < 64 && lane == dq) wa |= bitq;
-                if (lane == 0) { rowb[qw] = wb; rowa[w] = wa; }
-                if (carry && dq > 0 && dq < 64 && lane == dq) rowa[qw] = wa;
-                if (carry && dq >= 64 && lane == 0) rowa[qw] |= bitq;
-                if (lane == 0) rs[q] = (uint8_t)a;
-                if (((xm >> po) & 1) && lane == 0) {
-                    const uint8_t t = cs[p];
-                    cs[p] = cs[q];
-                    cs[q] = t;
-                }
-                wave_lds_order();
-                const int hb = first_set(wb, qw, Wd, rowb, lane);
-                int ha = first_set(wa, w, Wd, rowa, lane);
-                if (carry && dq >= 64) ha = min(ha, q);
-                hv = lane == b ? hb : hv;
-                hv = lane == a ? ha : hv;
-                if (dq == 0) {
-                    if (lane == (q & 63)) rv = a;
-                    if (!carry) mm &= ~bitq;
-                }
-            }
-        }
-        wave_lds_order();
     }
     // mutation: one valid swap with probability p_mut
     const u32x4 rm = philox((uint32_t)c, g, 1u, TAG_MUT, seed);
