@@ -14,10 +14,9 @@ goac_status build_ewald(goac_ctx*, const double*, int64_t, const double*, const 
 __global__ void k_init(int64_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
                        int32_t, const uint8_t*, uint64_t, uint32_t, uint32_t, uint8_t*);
 __global__ void k_ga_prep(int64_t, const double*, uint64_t*, int32_t*);
-__global__ void k_ga_child(int64_t, int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*,
-                           const uint8_t*, const int32_t*, const int32_t*, int32_t, const uint8_t*, int64_t,
-                           const uint8_t*, const uint64_t*, const int32_t*, int32_t, uint64_t, uint32_t, double,
-                           uint8_t*);
+size_t ga_child_lds(const goac_problem* pb);
+goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
+                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out);
 goac_status anchor_batched(goac_ctx*, goac_chains*, int, uint32_t);
 // rows of every group from its slot permutation (hybrid.hip)
 __global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __restrict__ slot,
@@ -808,11 +807,7 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
     if (P <= 0 || !pop_in || !E_in || !prm || !pop_out || pop_in == pop_out || !(prm->p_mut >= 0.0))
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
     if (P > (int64_t)1 << 30) return fail(ctx, GOAC_EINVAL, "ga_generation: population too large");
-    const ProblemDev& d = pb->d;
-    // child occupation, path copy and parent B (bytes), then the register walk's
-    // 16 x 64 words of species rows
-    const size_t lds = round_up(3 * round_up(d.M, 16), 16) + 8 * 16 * 64;
-    if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "ga_generation: too many mobile positions");
+    if (ga_child_lds(pb) > 160 * 1024) return fail(ctx, GOAC_EINVAL, "ga_generation: too many mobile positions");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     const int32_t ne = (int32_t)std::min<int64_t>(std::max(prm->n_elite, 0), P);
     void* ws = nullptr;
@@ -827,12 +822,7 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
     hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, cum, err);
     GOAC_CHECK_LAUNCH(ctx);
     GOAC_TRY(rank_select(ctx, P, E_in, ne, cnt, nullptr, elite, nullptr));
-    if (lds > 64 * 1024)
-        GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_ga_child, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_ga_child, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
-                       pb->spos_inv, d.msub, d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite, ne,
-                       prm->seed, prm->generation, prm->p_mut, pop_out);
-    GOAC_CHECK_LAUNCH(ctx);
+    GOAC_TRY(ga_children(pb, P, pop_in, cum, elite, ne, prm, pop_out));
     int32_t herr = 0;
     GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, ctx->stream));
     GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -152,10 +152,9 @@ __device__ inline int wave_find(int from, int len, Pred pred) {
 // it. Returns false on a species id out of range or a broken composition.
 constexpr int kRegSpecies = 16;
 constexpr int kRegMaxLen = 64 * 64;
-// below this length the scan walk is the faster one (measured per generation:
-// 256 positions 155 us vs 324 us, 2048 positions 830 us vs 698 us, for the 4x4x4
-// and 8x8x8 rock-salt populations)
-constexpr int kRegMinLen = 1024;
+// sublattices up to this length take the byte walk (crossover_bytes), longer ones
+// the register walk when it applies, else the scan walk
+constexpr int kByteMaxLen = 1024;
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
 
@@ -297,6 +296,84 @@ __device__ bool crossover_regs(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int 
     return true;
 }
 
+// Crossover walk of one sublattice of at most 256 NR positions held in registers,
+// any species count: lane l holds position l + 64 k of chunk k in byte k & 3 of
+// dword k >> 2 of R (the path copy), Bv (parent B) and Cv (the child). The coin
+// of every position is drawn up front, all lanes in parallel (bit k of coin). A
+// step finds the next disagreeing position p and its partner q with a ballot over
+// one chunk at a time and moves single bytes between lanes with readlane, so the
+// walk touches no memory between the loads and the final stores of the child.
+template <int NR>
+__device__ void crossover_bytes(uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s, uint32_t c,
+                                uint32_t g, uint64_t seed, int lane) {
+    uint32_t R[NR], Bv[NR], Cv[NR];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+        uint32_t r = 0xffffffffu, b = 0xffffffffu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = (4 * d + k) * 64 + lane;
+            if (x < len) {
+                const uint32_t sh = 8u * (uint32_t)k;
+                r = (r & ~(0xffu << sh)) | ((uint32_t)cs[x] << sh);
+                b = (b & ~(0xffu << sh)) | ((uint32_t)bs[x] << sh);
+            }
+        }
+        R[d] = r;  // padding bytes agree with B, so the walk never visits them
+        Bv[d] = b;
+        Cv[d] = r;
+    }
+    const int nk = (len + 63) >> 6;
+    uint32_t coin = 0;
+    for (int k = 0; k < nk; ++k) {
+        const int x = k * 64 + lane;
+        if (x < len && (philox((uint32_t)spos_s[x], c, g, TAG_X, seed).x >> 31)) coin |= 1u << k;
+    }
+    auto chunk = [](const uint32_t(&v)[NR], int k) -> uint32_t { return byte_of(v[k >> 2], k & 3); };
+    auto put = [lane](uint32_t(&v)[NR], int k, int l, uint32_t b) {
+        const uint32_t sh = 8u * (uint32_t)(k & 3);
+        const uint32_t old = v[k >> 2];
+        const uint32_t nv = (old & ~(0xffu << sh)) | (b << sh);
+        v[k >> 2] = lane == l ? nv : old;
+    };
+    int p = 0;
+    while (p < len) {
+        // next disagreeing position from p
+        int k = p >> 6;
+        uint64_t m = __ballot(chunk(R, k) != chunk(Bv, k)) & (~0ull << (p & 63));
+        while (!m && ++k < nk) m = __ballot(chunk(R, k) != chunk(Bv, k));
+        if (!m) break;
+        const int lp = (int)__ffsll((long long)m) - 1;
+        p = k * 64 + lp;
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)chunk(R, k), lp);
+        const uint32_t want = (uint32_t)__builtin_amdgcn_readlane((int)chunk(Bv, k), lp);
+        // partner: first q > p holding want in the path copy and disagreeing with B
+        int kq = k;
+        uint64_t mq = __ballot(chunk(R, kq) == want && chunk(R, kq) != chunk(Bv, kq));
+        mq = lp == 63 ? 0ull : mq & (~0ull << (lp + 1));
+        while (!mq && ++kq < nk) mq = __ballot(chunk(R, kq) == want && chunk(R, kq) != chunk(Bv, kq));
+        if (!mq) break;  // cannot happen: the path copy and B share the composition
+        const int lq = (int)__ffsll((long long)mq) - 1;
+        put(R, k, lp, want);
+        put(R, kq, lq, a);
+        if (((uint32_t)__builtin_amdgcn_readlane((int)coin, lp) >> k) & 1u) {
+            const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)chunk(Cv, k), lp);
+            const uint32_t cq = (uint32_t)__builtin_amdgcn_readlane((int)chunk(Cv, kq), lq);
+            put(Cv, k, lp, cq);
+            put(Cv, kq, lq, cp);
+        }
+        ++p;
+    }
+#pragma unroll
+    for (int d = 0; d < NR; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = (4 * d + k) * 64 + lane;
+            if (x < len) cs[x] = (uint8_t)byte_of(Cv[d], k);
+        }
+    wave_lds_order();
+}
+
 // Child c of generation g (SI, "Genetic Algorithm"). Children below n_elite copy
 // the elites. Every other child draws parents A and B by roulette, crosses them
 // and may mutate:
@@ -307,9 +384,11 @@ __device__ bool crossover_regs(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int 
 //     each swap of the path iff the top bit of Philox(p_mobile, c, g, X) is set.
 //   mutation: with probability p_mut one valid swap, drawn as an MC proposal
 //     with the sublattice's positions ordered by (species, position).
-// Sublattices of 1025..4096 positions with at most 16 species take the
-// register-resident walk (crossover_regs); others the scan walk, which finds p and
-// q with 64-position ballots over the path copy in LDS.
+// Sublattices of up to 1024 positions take the byte walk (crossover_bytes); those
+// of 1025..4096 positions with at most 16 species the species-row walk
+// (crossover_regs, compiled in only when REG); others the scan walk, which finds p
+// and q with 64-position ballots over the path copy in LDS.
+template <bool REG>
 __global__ __launch_bounds__(64) void k_ga_child(
     int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
     const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob,
@@ -365,7 +444,13 @@ __global__ __launch_bounds__(64) void k_ga_child(
         uint8_t* rs = rf + base;
         uint8_t* cs = ch + base;
         const uint8_t* bs = bb + base;
-        if (len > kRegMinLen && len <= kRegMaxLen && E <= kRegSpecies) {
+        if (len <= kByteMaxLen) {
+            if (len <= 256) crossover_bytes<1>(cs, bs, len, spos + base, (uint32_t)c, g, seed, lane);
+            else if (len <= 512) crossover_bytes<2>(cs, bs, len, spos + base, (uint32_t)c, g, seed, lane);
+            else crossover_bytes<4>(cs, bs, len, spos + base, (uint32_t)c, g, seed, lane);
+            continue;
+        }
+        if (REG && len <= kRegMaxLen && E <= kRegSpecies) {
             crossover_regs(rs, cs, bs, len, spos + base, mk, (uint32_t)c, g, seed, lane);
             continue;
         }
@@ -427,6 +512,39 @@ __global__ __launch_bounds__(64) void k_ga_child(
     }
     for (int x = lane; x < M; x += 64) out[mob[spos[x]]] = ch[x];
     for (int f = lane; f < n_fixed; f += 64) out[fixed_idx[f]] = ref_occ[fixed_idx[f]];
+}
+
+// The register walk's arrays take most of the register file (one wavefront per
+// SIMD), so its variant runs only for problems with a sublattice it walks.
+static bool ga_reg_walk(const goac_problem* pb) {
+    bool reg = false;
+    for (int s = 0; s < pb->d.S; ++s) {
+        const int len = pb->tab_host[2 + s];
+        reg = reg || (len > kByteMaxLen && len <= kRegMaxLen && pb->d.E <= kRegSpecies);
+    }
+    return reg;
+}
+
+// LDS of a child: its occupation, the path copy and parent B (bytes), then the
+// register walk's 16 x 64 words of species rows
+size_t ga_child_lds(const goac_problem* pb) {
+    return round_up(3 * round_up(pb->d.M, 16), 16) + (ga_reg_walk(pb) ? 8 * kRegSpecies * 64 : 0);
+}
+
+goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
+                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out) {
+    goac_ctx* ctx = pb->ctx;
+    const ProblemDev& d = pb->d;
+    const bool reg = ga_reg_walk(pb);
+    const size_t lds = ga_child_lds(pb);
+    const void* fn = reg ? (const void*)k_ga_child<true> : (const void*)k_ga_child<false>;
+    if (lds > 64 * 1024) GOAC_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    auto launch = reg ? k_ga_child<true> : k_ga_child<false>;
+    hipLaunchKernelGGL(launch, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
+                       pb->spos_inv, d.msub, d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite,
+                       n_elite, prm->seed, prm->generation, prm->p_mut, pop_out);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
 }
 
 // ------------------------------------------------------------------ ranking
