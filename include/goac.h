@@ -126,6 +126,10 @@ typedef struct {
     int32_t mixed_exact;    /* 1 if every shifted charge is bfloat16-exact     */
     int32_t reserved;
 } goac_problem_info;
+/* Sizes of a problem and its fixed-ion energy. E_ff is derived on the device by
+ * goac_problem_create, which returns without waiting for it; the first call here
+ * waits for the context's stream and reads it back (later calls return the
+ * stored value). Errors: EINVAL (null pointer), EHIP (the read-back failed). */
 goac_status goac_problem_get_info(const goac_problem* pb, goac_problem_info* out);
 
 /* Random valid starts (SI, "Random"): per chain c and sublattice s, the

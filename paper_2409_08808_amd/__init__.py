@@ -189,11 +189,28 @@ class Problem:
                                              self.species.ctypes.data_as(C.c_void_p), len(self.charge),
                                              self.charge.ctypes.data_as(C.c_void_p), C.byref(h)))
         self._h = h
-        info = ProblemInfo()
-        ctx.check(load().goac_problem_get_info(h, C.byref(info)))
-        self.M = int(info.M)
-        self.E_fixed = float(info.E_fixed)
-        self.mixed_exact = bool(info.mixed_exact)
+        self._info = None
+
+    def info(self):
+        """The problem's sizes and fixed-ion energy (the first call waits for the
+        stream: the energy is derived on the device)."""
+        if self._info is None:
+            info = ProblemInfo()
+            self.ctx.check(load().goac_problem_get_info(self._h, C.byref(info)))
+            self._info = info
+        return self._info
+
+    @property
+    def M(self):
+        return int(self.info().M)
+
+    @property
+    def E_fixed(self):
+        return float(self.info().E_fixed)
+
+    @property
+    def mixed_exact(self):
+        return bool(self.info().mixed_exact)
 
     def init_occupations(self, C_, seed, chain_base=0, instance=0):
         occ = torch.empty((C_, self.n), dtype=torch.uint8, device=self.ctx.device)
@@ -294,15 +311,19 @@ class Chains:
         self._kT = kT  # the library copies the table before returning; kept for clarity
         self.ctx.check(load().goac_mc_sweep(self._h, C.byref(prm)))
 
-    def export(self):
-        """(occupations, best occupations, stats) with stats a numpy structured array."""
+    def export(self, host_stats=True):
+        """(occupations, best occupations, stats) with stats a numpy structured array,
+        or, with host_stats=False, the raw uint8 device tensor (no wait for the stream)."""
         tot = sum(c * n for c, n in self._n_per)
         occ = torch.empty(tot, dtype=torch.uint8, device=self.ctx.device)
         best = torch.empty(tot, dtype=torch.uint8, device=self.ctx.device)
         st = torch.empty(self.C * STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.ctx.device)
         self.ctx.check(load().goac_chains_export(self._h, _ptr(occ), _ptr(best), _ptr(st)))
-        self.ctx.synchronize()
-        stats = st.cpu().numpy().view(STATS_DTYPE)
+        if host_stats:
+            self.ctx.synchronize()
+            stats = st.cpu().numpy().view(STATS_DTYPE)
+        else:
+            stats = st
         if len(self._n_per) == 1:
             c, n = self._n_per[0]
             occ, best = occ.view(c, n), best.view(c, n)

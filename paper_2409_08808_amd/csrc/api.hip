@@ -60,6 +60,47 @@ void pool_put(goac_ctx* ctx, void* p, size_t bytes) {
     ctx->pool_bytes += bytes;
 }
 
+// A copy from pinned memory is queued at once; one from pageable memory makes the
+// host wait. The ring's halves take turns: a half is written again only once the
+// event recorded when the copies from it were queued has completed, which the
+// stream has long passed unless a half's worth of uploads is still queued.
+goac_status upload(goac_ctx* ctx, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return GOAC_OK;
+    if (ctx->capturing) return fail(ctx, GOAC_EINVAL, "host copy inside a stream capture");
+    const size_t need = (size_t)round_up((int64_t)bytes, 256);
+    if (need > ctx->stage_half) {
+        if (ctx->stage) {
+            // queued copies may still read the old ring
+            GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            GOAC_HIP(ctx, hipHostFree(ctx->stage));
+            ctx->stage = nullptr;
+        }
+        const size_t half = std::max<size_t>((size_t)round_up((int64_t)need, 1 << 20), (size_t)4 << 20);
+        GOAC_HIP(ctx, hipHostMalloc((void**)&ctx->stage, 2 * half, hipHostMallocDefault));
+        ctx->stage_half = half;
+        ctx->stage_off = 0;
+        ctx->stage_cur = 0;
+        ctx->stage_pending[0] = ctx->stage_pending[1] = false;
+        for (int h = 0; h < 2; ++h)
+            if (!ctx->stage_ev[h]) GOAC_HIP(ctx, hipEventCreateWithFlags(&ctx->stage_ev[h], hipEventDisableTiming));
+    }
+    if (ctx->stage_off + need > ctx->stage_half) {
+        GOAC_HIP(ctx, hipEventRecord(ctx->stage_ev[ctx->stage_cur], ctx->stream));
+        ctx->stage_pending[ctx->stage_cur] = true;
+        ctx->stage_cur ^= 1;
+        ctx->stage_off = 0;
+        if (ctx->stage_pending[ctx->stage_cur]) {
+            GOAC_HIP(ctx, hipEventSynchronize(ctx->stage_ev[ctx->stage_cur]));
+            ctx->stage_pending[ctx->stage_cur] = false;
+        }
+    }
+    char* s = ctx->stage + (size_t)ctx->stage_cur * ctx->stage_half + ctx->stage_off;
+    std::memcpy(s, src, bytes);
+    GOAC_HIP(ctx, hipMemcpyAsync(dst, s, bytes, hipMemcpyHostToDevice, ctx->stream));
+    ctx->stage_off += need;
+    return GOAC_OK;
+}
+
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
     if (slot < 0 || slot >= kWsSlots) return fail(ctx, GOAC_EINVAL, "workspace slot");
     if (bytes > ctx->ws_size[slot]) {
@@ -246,8 +287,8 @@ __global__ void k_check_comp(int64_t n, int32_t M, int32_t S, int32_t E, const i
 }
 
 // mobile occupation, perm (positions of each sublattice sorted by (species,
-// position)) and, unless best is NULL, the best copy of one chain; one
-// wavefront per chain. Within a
+// position)) and, unless best is NULL, the best copy of one chain, and, unless sc
+// is NULL, its fresh scalars; one wavefront per chain. Within a
 // 64-position chunk the rank of a position among equal (sublattice, species)
 // keys is a popcount of a ballot; running counts carry across chunks.
 __global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_t Mp, int32_t S, int32_t E,
@@ -255,11 +296,20 @@ __global__ __launch_bounds__(64) void k_chain_setup(int64_t n, int32_t M, int32_
                                                     const uint8_t* __restrict__ msub, const uint8_t* __restrict__ occ,
                                                     int64_t first, const int64_t* __restrict__ offs,
                                                     uint8_t* __restrict__ occ_m, uint16_t* __restrict__ perm,
-                                                    uint8_t* __restrict__ best) {
+                                                    uint8_t* __restrict__ best, ChainScalars* __restrict__ sc,
+                                                    int32_t inst, uint32_t id_base) {
     __shared__ int next[kMaxSub * kMaxSpecies];
     const int64_t c = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t off = offs[first + c];
+    if (sc && lane == 0) {
+        // a new chain: counters zero, ids and offset set
+        ChainScalars z{};
+        z.inst = inst;
+        z.chain_id = id_base + (uint32_t)c;
+        z.off = off;
+        sc[first + c] = z;
+    }
     const uint8_t* row = occ + c * n;
     const int32_t* subsize = tab + 2;
     const int32_t* suboff = subsize + S;
@@ -303,7 +353,8 @@ __global__ __launch_bounds__(256) void k_chain_field(int32_t M, int32_t Mp, cons
                                                      const double* __restrict__ Phi, const double* __restrict__ h,
                                                      const double* __restrict__ rowabs, double qmax,
                                                      const uint8_t* __restrict__ msub,
-                                                     const double* __restrict__ phibar, double E_ff, int64_t first,
+                                                     const double* __restrict__ phibar, const double* __restrict__ Ed,
+                                                     int64_t first,
                                                      ChainScalars* __restrict__ sc, void* __restrict__ phi,
                                                      int reload, const uint8_t* __restrict__ occ_m,
                                                      uint8_t* __restrict__ best) {
@@ -339,7 +390,7 @@ __global__ __launch_bounds__(256) void k_chain_field(int32_t M, int32_t Mp, cons
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double E = E_ff + 0.5 * s_a[0];
+        const double E = Ed[0] + 0.5 * s_a[0];
         S->E = E;
         // a start sets the best; a reload replaces it only when strictly lower
         const bool better = !reload || E < S->best_E;
@@ -461,12 +512,6 @@ goac_status dalloc(goac_ctx* ctx, T** p, size_t count, DevAllocs* track = nullpt
     return GOAC_OK;
 }
 
-#define GOAC_TRY(expr)                        \
-    do {                                      \
-        goac_status s_ = (expr);              \
-        if (s_ != GOAC_OK) return s_;         \
-    } while (0)
-
 // Byte offsets of the sub-arrays of one device arena (256-byte aligned).
 struct ArenaPlan {
     size_t end = 0;
@@ -506,6 +551,9 @@ extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
     for (int q = 0; q < kWsSlots; ++q)
         if (ctx->ws[q]) (void)hipFree(ctx->ws[q]);
     for (auto& b : ctx->pool) (void)hipFree(b.second);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    for (int h = 0; h < 2; ++h)
+        if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
     delete ctx;
 }
 
@@ -693,10 +741,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     std::memcpy(img.data() + o_c, cvec.data(), Mp * 8);
     std::memcpy(img.data() + o_q, qref.data(), Mp * 8);
     hipStream_t sm = ctx->stream;
-    if (hipMemcpyAsync(base, img.data(), up_end, hipMemcpyHostToDevice, sm) != hipSuccess) {
-        ctx->err = "problem_create: upload failed";
-        return bail(GOAC_EHIP);
-    }
+    if (upload(ctx, base, img.data(), up_end) != GOAC_OK) return bail(GOAC_EHIP);
     {
         const int64_t tot = (int64_t)Mp * Mp;
         hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, sm, n, M, Mp, V, d.mob, d.V64,
@@ -712,14 +757,8 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
             ctx->err = "problem_create: launch failed";
             return bail(GOAC_EHIP);
         }
-        double sc[2];
-        if (hipMemcpyAsync(sc, w_out, 16, hipMemcpyDeviceToHost, sm) != hipSuccess ||
-            hipStreamSynchronize(sm) != hipSuccess) {
-            ctx->err = "problem_create: derivation failed";
-            return bail(GOAC_EHIP);
-        }
-        d.E_ff = sc[0];
-        d.E_t = sc[1];
+        // E_ff and E_t stay on the device; kernels read them there
+        d.Ed = w_out;
     }
     // ht beyond M is zero
     if (Mp > M && hipMemsetAsync(d.ht + M, 0, (Mp - M) * 8, sm) != hipSuccess) return bail(GOAC_EHIP);
@@ -741,7 +780,17 @@ extern "C" goac_status goac_problem_get_info(const goac_problem* pb, goac_proble
     out->M = pb->d.M;
     out->n_sublattices = pb->d.S;
     out->n_species = pb->d.E;
-    out->E_fixed = pb->d.E_ff;
+    if (!pb->e_host) {
+        double e[2];
+        if (hipSetDevice(pb->ctx->device) != hipSuccess ||
+            hipMemcpyAsync(e, pb->d.Ed, 16, hipMemcpyDeviceToHost, pb->ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(pb->ctx->stream) != hipSuccess)
+            return fail(pb->ctx, GOAC_EHIP, "problem_get_info: reading the fixed-ion energy failed");
+        pb->E_ff = e[0];
+        pb->E_t = e[1];
+        pb->e_host = true;
+    }
+    out->E_fixed = pb->E_ff;
     out->mixed_exact = pb->d.mixed_exact;
     out->reserved = 0;
     return GOAC_OK;
@@ -848,13 +897,14 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     }
     ch->total = tot;
     // one arena: the uploaded tables first (one copy), then the device-only state
+    // (the chain scalars are set by the setup kernel; one instance needs no order)
     ArenaPlan ap;
-    const size_t o_sc = ap.take(C * sizeof(ChainScalars));
     const size_t o_in = ap.take(n_inst * sizeof(McInst));
     const size_t o_of = ap.take(C * sizeof(int64_t));
-    const size_t o_or = ap.take(C * sizeof(int32_t));
-    const size_t o_q = ap.take(64 * sizeof(int32_t));
+    const size_t o_or = ap.take(n_inst > 1 ? C * sizeof(int32_t) : 0);
     const size_t up_end = ap.end;
+    const size_t o_q = ap.take(64 * sizeof(int32_t));
+    const size_t o_sc = ap.take(C * sizeof(ChainScalars));
     const size_t o_occ = ap.take(tot);
     const size_t o_perm = ap.take(tot * sizeof(uint16_t));
     const size_t o_best = ap.take(tot);
@@ -865,7 +915,7 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     ch->sc = (ChainScalars*)(base + o_sc);
     ch->insts = (McInst*)(base + o_in);
     ch->d_offs = (int64_t*)(base + o_of);
-    ch->order = (int32_t*)(base + o_or);
+    ch->order = n_inst > 1 ? (int32_t*)(base + o_or) : nullptr;
     ch->queue = (int32_t*)(base + o_q);
     ch->occ = (uint8_t*)(base + o_occ);
     ch->perm = (uint16_t*)(base + o_perm);
@@ -877,7 +927,7 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         const ProblemDev& d = ch->pbs[i]->d;
         McInst& I = insts[i];
         I.V64 = d.V64; I.V32 = d.V32; I.diag = d.diag; I.rowmax = d.rowmax; I.h = d.h; I.phibar = d.phibar;
-        I.msub = d.msub; I.tab = d.tab; I.charge = d.charge; I.E_ff = d.E_ff;
+        I.msub = d.msub; I.tab = d.tab; I.charge = d.charge; I.Ed = d.Ed;
         I.M = d.M; I.Mp = d.Mp; I.S = d.S; I.E = d.E;
         I.instance = ch->inst_id[i];
         I.pad_ = 0;
@@ -886,20 +936,16 @@ static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
         ch->max_E = std::max(ch->max_E, d.E);
         ch->max_tab = std::max(ch->max_tab, tab_words(d.S, d.E));
     }
-    ChainScalars* sc = (ChainScalars*)(host.data() + o_sc);
-    for (int64_t c = 0; c < C; ++c) {
-        sc[c].inst = ch->inst_of[c];
-        sc[c].chain_id = ch->chain_id[c];
-        sc[c].off = ch->offs[c];
-    }
     std::memcpy(host.data() + o_of, ch->offs.data(), C * 8);
-    // longest chains first (Mp as the cost), stable
-    int32_t* order = (int32_t*)(host.data() + o_or);
-    std::iota(order, order + C, 0);
-    std::stable_sort(order, order + C, [&](int32_t a, int32_t b) {
-        return ch->pbs[ch->inst_of[a]]->d.Mp > ch->pbs[ch->inst_of[b]]->d.Mp;
-    });
-    GOAC_HIP(ctx, hipMemcpyAsync(base, host.data(), up_end, hipMemcpyHostToDevice, sm));
+    if (n_inst > 1) {
+        // longest chains first (Mp as the cost), stable
+        int32_t* order = (int32_t*)(host.data() + o_or);
+        std::iota(order, order + C, 0);
+        std::stable_sort(order, order + C, [&](int32_t a, int32_t b) {
+            return ch->pbs[ch->inst_of[a]]->d.Mp > ch->pbs[ch->inst_of[b]]->d.Mp;
+        });
+    }
+    GOAC_TRY(upload(ctx, base, host.data(), up_end));
     return chains_fill(ch, occ, false);
 }
 
@@ -926,7 +972,8 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
                            d.msub, occ_i, err);
         hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)Ci), dim3(64), 0, sm, d.n, d.M, d.Mp, d.S, d.E, d.tab, d.mob,
                            d.msub, occ_i, ch->first_chain[i], ch->d_offs, ch->occ, ch->perm,
-                           reload ? nullptr : ch->best);
+                           reload ? nullptr : ch->best, reload ? nullptr : ch->sc, i,
+                           ch->chain_id[ch->first_chain[i]]);
         const size_t qb = (size_t)round_up((int64_t)Ci * d.Mp * 8, 256);
         void* ws = nullptr;
         GOAC_TRY(workspace(ctx, 0, 2 * qb, &ws));
@@ -936,11 +983,11 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
         GOAC_TRY(dgemm_nt(ctx, Ci, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr));
         if (mixed)
             hipLaunchKernelGGL(k_chain_field<true>, dim3((unsigned)Ci), dim3(256), 0, sm, d.M, d.Mp, Q, Phi, d.h,
-                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi,
+                               d.rowabs, d.qmax, d.msub, d.phibar, d.Ed, ch->first_chain[i], ch->sc, ch->phi,
                                reload ? 1 : 0, ch->occ, ch->best);
         else
             hipLaunchKernelGGL(k_chain_field<false>, dim3((unsigned)Ci), dim3(256), 0, sm, d.M, d.Mp, Q, Phi, d.h,
-                               d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->first_chain[i], ch->sc, ch->phi,
+                               d.rowabs, d.qmax, d.msub, d.phibar, d.Ed, ch->first_chain[i], ch->sc, ch->phi,
                                reload ? 1 : 0, ch->occ, ch->best);
         GOAC_CHECK_LAUNCH(ctx);
     }
@@ -1060,7 +1107,7 @@ extern "C" goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows
     void* ws = nullptr;
     GOAC_TRY(workspace(ctx, 0, (size_t)ch->C * 4, &ws));
     int32_t* d = (int32_t*)ws;
-    GOAC_HIP(ctx, hipMemcpyAsync(d, rows, ch->C * 4, hipMemcpyHostToDevice, ctx->stream));
+    GOAC_TRY(upload(ctx, d, rows, ch->C * 4));
     hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((ch->C + 255) / 256)), dim3(256), 0, ctx->stream, ch->C, d, ch->sc);
     GOAC_CHECK_LAUNCH(ctx);
     ch->max_row = 0;
@@ -1138,7 +1185,7 @@ static goac_status sweep_upload_kT(goac_chains* ch, const double* kT_host, size_
         ch->kT = (double*)p;
         ch->kT_cap = bytes / 8;
     }
-    GOAC_HIP(ctx, hipMemcpyAsync(ch->kT, kT_host, nkT * 8, hipMemcpyHostToDevice, ctx->stream));
+    GOAC_TRY(upload(ctx, ch->kT, kT_host, nkT * 8));
     return GOAC_OK;
 }
 
@@ -1320,7 +1367,7 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
             ch->ladder_cap = bytes / 8;
         }
         ch->ladder_last.assign(kT_host, kT_host + R);
-        GOAC_HIP(ctx, hipMemcpyAsync(ch->ladder, kT_host, R * 8, hipMemcpyHostToDevice, ctx->stream));
+        GOAC_TRY(upload(ctx, ch->ladder, kT_host, R * 8));
     }
     const double* d = ch->ladder;
     const int64_t ng = ch->C / R;
@@ -1388,6 +1435,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ctx->stream = cap;
+    ctx->capturing = true;
     goac_status st = GOAC_OK;
     hipError_t ec = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (ec == hipSuccess) {
@@ -1400,6 +1448,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
         ec = hipStreamEndCapture(cap, &graph);
     }
     ctx->stream = sm;
+    ctx->capturing = false;
     if (st == GOAC_OK && ec == hipSuccess) ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     for (uint64_t r = 0; st == GOAC_OK && ec == hipSuccess && r < rounds; ++r) ec = hipGraphLaunch(exec, sm);
     if (st == GOAC_OK && ec == hipSuccess) ec = hipStreamSynchronize(sm);

@@ -123,8 +123,7 @@ struct ProblemDev {
     double* charge;      // E
     double* dq;          // S x E: charge[e] - c_s
     int32_t* tab;        // sublattice tables (tab_words)
-    double E_ff;         // energy of the fixed ions
-    double E_t;          // E_ff + c^T h + 1/2 c^T V_mm c
+    const double* Ed;    // 2: E_ff (energy of the fixed ions), E_t = E_ff + c^T h + 1/2 c^T V_mm c
     double qmax;         // max |charge|
     int mixed_exact;
 };
@@ -154,7 +153,7 @@ struct McInst {
     const uint8_t* msub;
     const int32_t* tab;
     const double* charge;
-    double E_ff;
+    const double* Ed;       // E_ff, E_t of the instance
     int32_t M, Mp, S, E;
     uint32_t instance;      // instance id in the Philox counters
     int32_t pad_;
@@ -173,6 +172,14 @@ struct goac_ctx {
     size_t ws_size[kWsSlots] = {0, 0, 0};
     std::multimap<size_t, void*> pool;  // released arenas by size, reused by later ones
     size_t pool_bytes = 0;
+    // pinned staging of host-to-device copies: two halves, each with the event
+    // recorded after the copies last queued from it
+    char* stage = nullptr;
+    size_t stage_half = 0, stage_off = 0;
+    int stage_cur = 0;
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_pending[2] = {false, false};
+    bool capturing = false;  // a stream capture is open on the context's work
 };
 
 struct goac_problem {
@@ -186,6 +193,8 @@ struct goac_problem {
     int32_t* spos_inv = nullptr;     // M: index of position k in spos
     int32_t* fixed_idx = nullptr;    // fixed sites
     int32_t n_fixed = 0;
+    mutable bool e_host = false;     // E_ff, E_t read back (on the first request)
+    mutable double E_ff = 0.0, E_t = 0.0;
     void* arena = nullptr;           // one allocation holding every device array
     size_t arena_bytes = 0;
 };
@@ -248,6 +257,13 @@ inline goac_status fail(goac_ctx* ctx, goac_status st, const std::string& msg) {
 
 #define GOAC_CHECK_LAUNCH(ctx) GOAC_HIP(ctx, hipGetLastError())
 
+// propagate a failed status
+#define GOAC_TRY(expr)                \
+    do {                              \
+        goac_status s_ = (expr);      \
+        if (s_ != GOAC_OK) return s_; \
+    } while (0)
+
 // Monte Carlo launch arguments
 struct McArgs {
     const McInst* insts;
@@ -283,6 +299,8 @@ goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
 // arenas of problems and chain sets: a block released to the context is handed to
 // the next arena that fits in it (at most twice its size); *bytes is rounded up
 goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out);
+// stream-ordered copy of host memory to the device through the pinned staging ring
+goac_status upload(goac_ctx* ctx, void* dst, const void* src, size_t bytes);
 void pool_put(goac_ctx* ctx, void* p, size_t bytes);
 
 // population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies

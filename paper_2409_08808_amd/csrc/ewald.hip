@@ -186,12 +186,11 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
             cpos[3 * i + k] = frac[3 * i] * c.A[0][k] + frac[3 * i + 1] * c.A[1][k] + frac[3 * i + 2] * c.A[2][k];
-    GOAC_HIP(ctx, hipMemcpyAsync(d_frac, frac.data(), frac.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-    GOAC_HIP(ctx, hipMemcpyAsync(d_pos, cpos.data(), cpos.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-    if (!trans.empty())
-        GOAC_HIP(ctx, hipMemcpyAsync(d_tr, trans.data(), trans.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-    if (!G.empty()) GOAC_HIP(ctx, hipMemcpyAsync(d_G, G.data(), G.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-    GOAC_HIP(ctx, hipMemcpyAsync(d_A, &c.A[0][0], 9 * 8, hipMemcpyHostToDevice, ctx->stream));
+    GOAC_TRY(upload(ctx, d_frac, frac.data(), frac.size() * 8));
+    GOAC_TRY(upload(ctx, d_pos, cpos.data(), cpos.size() * 8));
+    GOAC_TRY(upload(ctx, d_tr, trans.data(), trans.size() * 8));
+    GOAC_TRY(upload(ctx, d_G, G.data(), G.size() * 8));
+    GOAC_TRY(upload(ctx, d_A, &c.A[0][0], 9 * 8));
     const double cst = -ke * kPi / (c.vol * alpha * alpha);
     const double self = ke * 2.0 * alpha / std::sqrt(kPi);
     {
@@ -210,9 +209,7 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
         st = dgemm_nt(ctx, n, n, ld, d_T, ld, d_T, ld, V, n, 1.0, 1.0, nullptr);
         if (st != GOAC_OK) return st;
     }
-    // the workspace may be reused by the next call on this stream; host vectors are
-    // released here, so wait for the copies to complete
-    GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // the uploads came from the staging ring, so the host vectors may go now
     return GOAC_OK;
 }
 

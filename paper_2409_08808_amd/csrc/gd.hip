@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kGdThreads) void k_gd(int64_t n, int32_t M, int32_t
                                                    const uint8_t* __restrict__ msub_g,
                                                    const double* __restrict__ V64, const double* __restrict__ diag,
                                                    const double* __restrict__ h, const double* __restrict__ charge,
-                                                   double E_ff, int64_t max_steps, double tol,
+                                                   const double* __restrict__ Ed, int64_t max_steps, double tol,
                                                    uint8_t* __restrict__ occ, int64_t* __restrict__ steps_out,
                                                    double* __restrict__ E_out) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kGdThreads) void k_gd(int64_t n, int32_t M, int32_t
     double Ecur = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) Ecur += s_red[w];
-    Ecur = E_ff + 0.5 * Ecur;
+    Ecur = Ed[0] + 0.5 * Ecur;
     __syncthreads();
 
     auto score = [&](int i, int j, double& dE) -> bool {
@@ -162,7 +162,7 @@ extern "C" goac_status goac_gd_run(goac_problem* pb, int64_t P, uint8_t* occ_dev
     if (lds > 64 * 1024)
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_gd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_gd, dim3((unsigned)P), dim3(kGdThreads), lds, ctx->stream, d.n, d.M, d.Mp, d.E, d.mob,
-                       d.msub, d.V64, d.diag, d.h, d.charge, d.E_ff, max_steps, tol, occ_dev, steps_dev, E_dev);
+                       d.msub, d.V64, d.diag, d.h, d.charge, d.Ed, max_steps, tol, occ_dev, steps_dev, E_dev);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

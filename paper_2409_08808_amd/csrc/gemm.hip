@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32
 __global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int32_t Mp, int32_t n_tiles,
                                                       const __hip_bfloat16* __restrict__ dQ,
                                                       const double* __restrict__ ht, const double* __restrict__ part,
-                                                      const double* __restrict__ lin, double E_t,
+                                                      const double* __restrict__ lin, const double* __restrict__ Ed,
                                                       double* __restrict__ E) {
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int3
     for (int t = lane; t < n_tiles; t += 64) s += part[(int64_t)t * P + p];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) E[p] = E_t + (lin ? lin[p] + s : s);
+    if (lane == 0) E[p] = Ed[1] + (lin ? lin[p] + s : s);
 }
 
 // dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M; grid (Mp/512, P),
@@ -449,7 +449,7 @@ __global__ void k_build_q64(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t
 __global__ __launch_bounds__(256) void k_pop_fp64_finalize(int64_t P, int32_t M, int32_t Mp,
                                                            const double* __restrict__ Q,
                                                            const double* __restrict__ Phi,
-                                                           const double* __restrict__ h, double E_ff,
+                                                           const double* __restrict__ h, const double* __restrict__ Ed,
                                                            double* __restrict__ E) {
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256) void k_pop_fp64_finalize(int64_t P, int32_t M,
     for (int k = lane; k < M; k += 64) s += Q[p * Mp + k] * (h[k] + 0.5 * Phi[p * Mp + k]);
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) E[p] = E_ff + s;
+    if (lane == 0) E[p] = Ed[0] + s;
 }
 
 goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
@@ -529,16 +529,10 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
                        part, (int32_t)MT, S, kps, order);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
-                       n_parts, dQ, d.ht, part, lin, d.E_t, E);
+                       n_parts, dQ, d.ht, part, lin, d.Ed, E);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
-
-#define GOAC_TRY_(expr)                \
-    do {                               \
-        goac_status s_ = (expr);       \
-        if (s_ != GOAC_OK) return s_;  \
-    } while (0)
 
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
     goac_ctx* ctx = pb->ctx;
@@ -549,11 +543,11 @@ goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, doubl
     if (st != GOAC_OK) return st;
     double* Q = (double*)ws;
     double* Phi = (double*)((char*)ws + qb);
-    GOAC_TRY_(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q));
+    GOAC_TRY(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q));
     st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr);
     if (st != GOAC_OK) return st;
     hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M,
-                       d.Mp, Q, Phi, d.h, d.E_ff, E);
+                       d.Mp, Q, Phi, d.h, d.Ed, E);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

@@ -16,12 +16,6 @@
 
 #include "common.h"
 
-#define GOAC_TRY_H(expr)               \
-    do {                               \
-        goac_status s_ = (expr);       \
-        if (s_ != GOAC_OK) return s_;  \
-    } while (0)
-
 namespace goac {
 
 // rows of every group from its slot permutation (a non-permutation is left alone)
@@ -70,7 +64,7 @@ static goac_status chains_scratch(goac_chains* ch, size_t bytes, void** out) {
         ch->scratch = nullptr;
         ch->scratch_size = 0;
         size_t got = bytes;
-        GOAC_TRY_H(pool_get(ctx, &got, &ch->scratch));
+        GOAC_TRY(pool_get(ctx, &got, &ch->scratch));
         ch->scratch_size = got;
     }
     *out = ch->scratch;
@@ -102,7 +96,7 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     const size_t b_cand = round_up(PC * n, 256), b_E = round_up(PC * 8, 256), b_idx = round_up(PC * 8, 256);
     const size_t b_cnt = round_up(PC * 4, 256), b_pop = round_up(P * n, 256), b_occ = round_up(C * n, 256);
     void* base = nullptr;
-    GOAC_TRY_H(chains_scratch(ch, b_cand + b_E + b_idx + b_cnt + b_pop + b_occ, &base));
+    GOAC_TRY(chains_scratch(ch, b_cand + b_E + b_idx + b_cnt + b_pop + b_occ, &base));
     uint8_t* cand = (uint8_t*)base;
     double* Ecand = (double*)((char*)base + b_cand);
     int64_t* idx = (int64_t*)((char*)base + b_cand + b_E);
@@ -124,16 +118,16 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
             mp.n_blocks = 1;
             mp.block_len = (uint64_t)prm->trials;
             mp.reanchor_every = prm->reanchor_every > 0 ? prm->reanchor_every : 1024;
-            GOAC_TRY_H(goac_mc_sweep(ch, &mp));
+            GOAC_TRY(goac_mc_sweep(ch, &mp));
         }
-        GOAC_TRY_H(goac_remc_exchange(ch, R, prm->kT_host, prm->round * (uint64_t)prm->exchanges + (uint64_t)e,
+        GOAC_TRY(goac_remc_exchange(ch, R, prm->kT_host, prm->round * (uint64_t)prm->exchanges + (uint64_t)e,
                                       prm->seed, slot_dev, nullptr));
     }
     // 2. REMC -> GA: the P lowest of the population and the chains' bests
     GOAC_HIP(ctx, hipMemcpyAsync(cand, pop_dev, (size_t)(P * n), hipMemcpyDeviceToDevice, sm));
-    GOAC_TRY_H(goac_chains_export(ch, nullptr, cand + P * n, nullptr));
-    GOAC_TRY_H(energies_fp64(pb, PC, cand, Ecand));
-    GOAC_TRY_H(rank_select(ctx, PC, Ecand, (int32_t)P, cnt, idx, nullptr, E_dev));
+    GOAC_TRY(goac_chains_export(ch, nullptr, cand + P * n, nullptr));
+    GOAC_TRY(energies_fp64(pb, PC, cand, Ecand));
+    GOAC_TRY(rank_select(ctx, PC, Ecand, (int32_t)P, cnt, idx, nullptr, E_dev));
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)P), dim3(256), 0, sm, P, n, idx, cand, pop_dev);
     GOAC_CHECK_LAUNCH(ctx);
     // 3. GA phase (double-buffered; the result ends in pop_dev)
@@ -145,15 +139,15 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
         gp.generation = (uint32_t)(prm->round * (uint64_t)prm->generations + (uint64_t)k);
         gp.n_elite = prm->n_elite;
         gp.p_mut = prm->p_mut;
-        GOAC_TRY_H(goac_ga_generation(pb, P, cur, E_dev, &gp, other));
-        GOAC_TRY_H(goac_energies(pb, P, other, (goac_precision)prm->precision, E_dev));
+        GOAC_TRY(goac_ga_generation(pb, P, cur, E_dev, &gp, other));
+        GOAC_TRY(goac_energies(pb, P, other, (goac_precision)prm->precision, E_dev));
         std::swap(cur, other);
     }
     if (cur != pop_dev) GOAC_HIP(ctx, hipMemcpyAsync(pop_dev, cur, (size_t)(P * n), hipMemcpyDeviceToDevice, sm));
     // 4. GA -> REMC: the best individuals to the groups' coldest replicas
     const int32_t n_inj = (int32_t)std::max<int64_t>(1, std::min<int64_t>(prm->inject, P));
-    GOAC_TRY_H(rank_select(ctx, P, E_dev, n_inj, cnt, idx, nullptr, nullptr));
-    GOAC_TRY_H(goac_chains_export(ch, occ_buf, nullptr, nullptr));
+    GOAC_TRY(rank_select(ctx, P, E_dev, n_inj, cnt, idx, nullptr, nullptr));
+    GOAC_TRY(goac_chains_export(ch, occ_buf, nullptr, nullptr));
     hipLaunchKernelGGL(k_inject, dim3((unsigned)G), dim3(256), 0, sm, G, R, n_inj, n, slot_dev, idx, pop_dev, E_dev,
                        ch->sc, occ_buf);
     GOAC_CHECK_LAUNCH(ctx);

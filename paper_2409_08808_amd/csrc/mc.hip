@@ -82,6 +82,27 @@ __device__ inline double wg_max(double x, double* scr) {
 constexpr double kU32 = 0x1p-24;      // unit roundoff of FP32
 constexpr double kMargin = 1e-8;      // eV: covers the reference FP64 chain's own rounding
 
+// Bounds of the Metropolis threshold L = -kT ln u (u = unit_open(r.z, r.w)) from
+// the top 24 bits ub of u, in FP32:
+//   thr = kT32 (-lg2 kLn2Up + b) >= L,   lo = kT32 (-lg2 kLn2Dn - b) <= L (ub >= 2)
+// with u32 = (ub + 1/2) 2^-24, lg2 the hardware log2(u32), ri >= 1/u32 the power of
+// two read off u32's exponent and b = 2^-24 ri + 2^-20. For ub >= 2, u lies within
+// 2^-25 of u32, so |ln u - ln u32| <= 0.625 2^-24 / u32, which the 2^-24 ri term
+// covers; the relative errors (log2 within 2^-23, kT32, the fma and the product,
+// 2^-24 each) stay below the 2^-20 of kLn2Up / kLn2Dn around ln 2, and the
+// absolute 2^-20 kT32 covers the log near u = 1. Trials with ub < 2 always stop.
+constexpr float kLn2Up = 0x1.62e448p-1f;  // >= ln 2 (1 + 2^-20)
+constexpr float kLn2Dn = 0x1.62e418p-1f;  // <= ln 2 (1 - 2^-20)
+// kT of the filter in FP32; below 2^-100 the bounds could lose their range, so the
+// filter then passes every trial to the exact rule
+__device__ __forceinline__ float kt_filter(double kT) { return kT >= 0x1p-100 ? (float)kT : INFINITY; }
+__device__ __forceinline__ void metropolis_band(uint32_t ub, float& lg2, float& b) {
+    const float u32 = fmaf((float)ub, 0x1p-24f, 0x1p-25f);
+    lg2 = __builtin_amdgcn_logf(u32);
+    const float ri = __uint_as_float(0x7f000000u - (__float_as_uint(u32) & 0x7f800000u));
+    b = fmaf(ri, 0x1p-24f, 0x1p-20f);
+}
+
 // FP64 anchor of a chain: phi_k = h_k + sum_l V64[l][k] q_l (V symmetric, so the
 // column walk is coalesced), phi' = phi - phibar_s stored as FP32; returns the new
 // energy E = E_ff + 1/2 sum q_k (phi_k + h_k) and the error bound eps of phi'32.
@@ -119,7 +140,7 @@ __device__ void anchor_chain(const McInst& I, const uint8_t* occ, const uint8_t*
     esum = wg_sum<WG>(esum, scr);
     pmax = wg_max<WG>(pmax, scr);
     amax = wg_max<WG>(amax, scr);
-    E_out = I.E_ff + 0.5 * esum;
+    E_out = I.Ed[0] + 0.5 * esum;
     // FP64 dot error (gamma_M times the absolute sum) plus FP32 rounding of phi'
     const double gM = (double)(M + 2) * 0x1p-53 * 1.01;
     eps_out = kU32 * pmax * 1.0001 + gM * amax * 2.0;
@@ -162,7 +183,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             __syncthreads();
             if (tid == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
             __syncthreads();
-            item = s_item;
+            item = __builtin_amdgcn_readfirstlane(s_item);
         }
         if (item >= a.n_items) return;
         const int c = a.order ? a.order[item] : item;
@@ -206,6 +227,12 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         uint64_t n_acc = sc->accepts, n_upd = sc->updates, n_fb = sc->fallbacks, n_anc = sc->anchors;
         double eps = sc->eps;
         float phib = sc->phibound;
+        // MIXED: the largest |V_kl| of any row, for the error bound of an update
+        double rmax = 0.0;
+        if constexpr (MIXED) {
+            for (int k = tid; k < M; k += WG) rmax = fmax(rmax, (double)rowmax[k]);
+            rmax = wg_max<WG>(rmax, s_scr);
+        }
         uint32_t since = sc->since_anchor;
         int status = sc->status;
         const GOAC_GLOBAL double* kTrow = gptr(a.kT + (int64_t)sc->row * a.n_blocks);
@@ -221,64 +248,68 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         const bool wide_blocks = a.block_len >= (uint64_t)WG;
         const uint64_t nb1 = (uint64_t)(a.n_blocks - 1);
         double kT0 = 0.0, kT1 = 0.0;   // temperatures of blocks blk0 and blk0 + 1
+        float kTf0 = 0.0f, kTf1 = 0.0f;
         uint64_t kblk = ~(uint64_t)0;
+        double eps2 = 2.0 * eps;
         while (t < t_end) {
+            const uint64_t left = t_end - t;
+            const int nvalid = left < (uint64_t)WG ? (int)left : WG;
             const uint64_t tl = t + (uint64_t)tid;
-            const bool valid = tl < t_end;
-            double kT;
+            // lanes from `split` on lie in block blk0 + 1
+            int split = WG;
+            float kTf;
             if (wide_blocks) {
                 if (blk0 != kblk) {
                     kT0 = kTrow[blk0 < nb1 ? blk0 : nb1];
                     kT1 = kTrow[blk0 + 1 < nb1 ? blk0 + 1 : nb1];
+                    kTf0 = kt_filter(kT0);
+                    kTf1 = kt_filter(kT1);
                     kblk = blk0;
                 }
-                kT = tl >= bnd ? kT1 : kT0;
+                const uint64_t rel = bnd - t;
+                split = rel < (uint64_t)WG ? (int)rel : WG;
+                kTf = tid < split ? kTf0 : kTf1;
             } else {
                 const uint64_t blk = tl / a.block_len;
-                kT = kTrow[blk < nb1 ? blk : nb1];
+                kTf = kt_filter(kTrow[blk < nb1 ? blk : nb1]);
             }
             const u32x4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), chain_id, w3, a.seed);
             const int i = (int)mulshift(r.x, (uint32_t)M);
+            // the loads that need only i go out first
+            const double Vii = diag[i];
+            const double phi_i = (double)phi[i];
             const int s = S == 1 ? 0 : msub[i];
             const int sa = occ[i];
+            const double qa = chg[sa];
             // s < 16, E < 256, positions < 2^16: 24-bit products run at the full
             // vector rate (32-bit integer products run at a quarter of it)
             const int se = (int)__umul24((unsigned)s, (unsigned)E) + sa;
             const int na = cnt[se];
             const int csz = subsize[s] - na;
-            int j = i;
-            bool stop = false;
-            double d = 0.0, dE = 0.0, e = 0.0, L32 = 0.0, m32 = 0.0;
-            if (valid && csz > 0) {
-                const int k = (int)mulshift(r.y, (uint32_t)csz);
-                const int idx = k < offs[se] ? k : k + na;
-                j = perm[suboff[s] + idx];
-                const int sb = occ[j];
-                d = chg[sb] - chg[sa];
-                const double phi_i = (double)phi[i], phi_j = (double)phi[j];
-                const double Vii = diag[i], Vjj = diag[j];
-                const double Vij = V64[__umul24((unsigned)i, (unsigned)Mp) + (unsigned)j];
-                dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
-                // Metropolis threshold L = -kT ln u, first in FP32 from the top 24 bits
-                // of u: |L32 - L| <= m32. u32 lies within 2^-25 of u, so its logarithm
-                // is off by at most 0.625 2^-24 / u32 (ub >= 2); the hardware log2
-                // (1 ulp), the product with ln 2 and with kT add at most 2^-21 relative,
-                // half the band's 2^-20. Tests closer than m32 to the threshold use the
-                // exact FP64 rule.
-                const uint32_t ub = r.z >> 8;
-                const float u32 = ((float)ub + 0.5f) * 0x1p-24f;
-                const float lg = __builtin_amdgcn_logf(u32) * 0.693147182f;
-                const float kTf = (float)kT;
-                L32 = (double)(-kTf * lg);
-                m32 = ub < 2 ? INFINITY
-                             : (double)(kTf * (0x1p-24f * __builtin_amdgcn_rcpf(u32) + 0x1p-20f * (1.0f - lg)));
-                // e bounds the FP32 field's error in dE (MIXED). The rule accepts iff
-                // dE < L (L > 0 covers dE <= 0), so a trial is surely rejected when
-                // dE - e > L32 + m32; every other trial stops the window and the first
-                // of them is resolved below.
-                if constexpr (MIXED) e = d != 0.0 ? 2.0 * fabs(d) * eps + kMargin : 0.0;
-                stop = !(dE - e > L32 + m32);
-            }
+            // scored without a branch: with csz == 0 the pick reads an in-range slot
+            // (perm is followed by where in LDS) and j falls back to i; such lanes and
+            // lanes past the end never stop
+            const int k = (int)mulshift(r.y, (uint32_t)csz);
+            const int idx = k < offs[se] ? k : k + na;
+            const int jp = perm[suboff[s] + idx];
+            const int j = csz > 0 ? jp : i;
+            const double Vjj = diag[j];
+            const double Vij = V64[__umul24((unsigned)i, (unsigned)Mp) + (unsigned)j];
+            const double phi_j = (double)phi[j];
+            const int sb = occ[j];
+            const double d = chg[sb] - qa;
+            const double dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
+            // Metropolis threshold L = -kT ln u: an FP32 upper bound thr >= L from the
+            // top 24 bits of u (metropolis_band); a trial is surely rejected when
+            // dE - e > thr, e bounding the FP32 field's error in dE (MIXED). Every
+            // other trial stops the window and the first of them is resolved below.
+            const uint32_t ub = r.z >> 8;
+            float lg2, b;
+            metropolis_band(ub, lg2, b);
+            const double thr = (double)(kTf * fmaf(-lg2, kLn2Up, b));
+            double e = 0.0;
+            if constexpr (MIXED) e = fma(fabs(d), eps2, kMargin);
+            const bool stop = tid < nvalid && csz > 0 && (ub < 2 || !(dE - e > thr));
             // first trial of the window that may be accepted
             const uint64_t mask = __ballot(stop);
             int f;
@@ -292,17 +323,23 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 for (int q = 0; q < NW; ++q) f = min(f, s_first[parity][q]);
                 parity ^= 1;
             }
-            const uint64_t left = t_end - t;
-            const int nvalid = left < (uint64_t)WG ? (int)left : WG;
-            if (TRACE && valid && tid < f) hsum += trial_hash(tl, (uint32_t)i, (uint32_t)j, 0u);
+            if (TRACE && tid < nvalid && tid < f) hsum += trial_hash(tl, (uint32_t)i, (uint32_t)j, 0u);
             if (f >= nvalid) {
                 t += (uint64_t)nvalid;
                 while (t >= bnd) { ++blk0; bnd += a.block_len; }
                 continue;
             }
             if (tid == f) {
-                // sure accept: even dE + e lies below the threshold band
-                const bool sure = (dE + e <= 0.0) || (dE + e - L32 < -m32);
+                double kT;
+                if (wide_blocks) {
+                    kT = f < split ? kT0 : kT1;
+                } else {
+                    const uint64_t blk = tl / a.block_len;
+                    kT = kTrow[blk < nb1 ? blk : nb1];
+                }
+                // sure accept: even dE + e lies below the lower bound of L
+                const double lo = (double)(kTf * fmaf(-lg2, kLn2Dn, -b));
+                const bool sure = d == 0.0 || dE + e <= 0.0 || (ub >= 2 && kTf < INFINITY && dE + e < lo);
                 s_b.i = i; s_b.j = j; s_b.unsure = sure ? 0 : 1;
                 s_b.d = d; s_b.dE = dE; s_b.u = unit_open(r.z, r.w); s_b.kT = kT;
             }
@@ -328,6 +365,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             }
             if (TRACE && tid == f) hsum += trial_hash(tl, (uint32_t)bi, (uint32_t)bj, accf ? 1u : 0u);
             if (accf) {
+                bool grew = false;   // MIXED: some |phi'| passed phib
                 if (bd != 0.0) {
                     const T dd = (T)bd;
                     const GOAC_GLOBAL T* Vi;
@@ -382,7 +420,10 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                             }
                         }
                     }
-                    if (MIXED && over) s_flag = 1;
+                    if constexpr (MIXED) {
+                        if constexpr (NW == 1) grew = __ballot(over) != 0;
+                        else if (over) s_flag = 1;
+                    }
                     ++n_upd;
                     ++since;
                 }
@@ -400,8 +441,8 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 ++n_acc;
                 __syncthreads();
                 if constexpr (MIXED) if (bd != 0.0) {
-                    const int flag = s_flag;
-                    if (flag) {
+                    if constexpr (NW > 1) grew = s_flag != 0;
+                    if (grew) {
                         // |phi'| grew past the bound: take the exact maximum
                         double pm = 0.0;
                         for (int k = tid; k < M; k += WG) pm = fmax(pm, fabs((double)phi[k]));
@@ -409,14 +450,14 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                         float pb = phib;
                         while ((double)pb < 2.0 * pm) pb *= 2.0f;
                         phib = pb;
-                        __syncthreads();
-                        if (tid == 0) s_flag = 0;
+                        if constexpr (NW > 1) {
+                            __syncthreads();
+                            if (tid == 0) s_flag = 0;
+                        }
                     }
                     // two fused multiply-adds per element, each rounding <= u |intermediate|,
-                    // plus the FP32 rounding of the two V entries
-                    const double rmi = (double)rowmax[bi], rmj = (double)rowmax[bj];
-                    const double ad = fabs(bd);
-                    eps += kU32 * (2.0 * (double)phib + ad * (rmi + 2.0 * (rmi + rmj))) * 1.0001;
+                    // plus the FP32 rounding of the two V entries (rows bounded by rmax)
+                    eps += kU32 * (2.0 * (double)phib + fabs(bd) * (5.0 * rmax)) * 1.0001;
                     if (!(eps < 1e3)) status = 1;
                     if (a.inline_anchor && since >= (uint32_t)a.reanchor_every) {
                         __syncthreads();
@@ -426,6 +467,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                         ++n_anc;
                         __syncthreads();
                     }
+                    eps2 = 2.0 * eps;
                 }
                 if (Ecur < best) {
                     best = Ecur;
@@ -499,7 +541,7 @@ __global__ __launch_bounds__(256) void k_anchor_apply(int32_t M, int32_t Mp, int
                                                       const double* __restrict__ Phi, const double* __restrict__ h,
                                                       const double* __restrict__ rowabs, double qmax,
                                                       const uint8_t* __restrict__ msub,
-                                                      const double* __restrict__ phibar, double E_ff,
+                                                      const double* __restrict__ phibar, const double* __restrict__ Ed,
                                                       ChainScalars* __restrict__ sc, float* __restrict__ phi) {
     __shared__ double s_a[256], s_b[256], s_c[256];
     const int r = blockIdx.x;
@@ -529,7 +571,7 @@ __global__ __launch_bounds__(256) void k_anchor_apply(int32_t M, int32_t Mp, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        S->E = E_ff + 0.5 * s_a[0];
+        S->E = Ed[0] + 0.5 * s_a[0];
         const double gM = (double)(M + 2) * 0x1p-53 * 1.01;
         S->eps = kU32 * s_b[0] * 1.0001 + gM * s_c[0] * 2.0;
         float pb = 1.0f;
@@ -567,7 +609,7 @@ goac_status anchor_batched(goac_ctx* ctx, goac_chains* ch, int inst, uint32_t R)
     st = dgemm_nt(ctx, Ci, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, due);
     if (st != GOAC_OK) return st;
     hipLaunchKernelGGL(k_anchor_apply, dim3((unsigned)Ci), dim3(256), 0, ctx->stream, d.M, d.Mp, first, due, Q, Phi,
-                       d.h, d.rowabs, d.qmax, d.msub, d.phibar, d.E_ff, ch->sc, (float*)ch->phi);
+                       d.h, d.rowabs, d.qmax, d.msub, d.phibar, d.Ed, ch->sc, (float*)ch->phi);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
