@@ -811,7 +811,7 @@ extern "C" goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     if (lds > 64 * 1024)
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_init, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_init, dim3((unsigned)(C * d.S)), dim3(256), lds, ctx->stream, d.n, d.S, d.E, d.tab, pb->spos,
+    hipLaunchKernelGGL(k_init, dim3((unsigned)(C * d.S)), dim3(64), lds, ctx->stream, d.n, d.S, d.E, d.tab, pb->spos,
                        d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, seed, chain_base, instance, occ);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
@@ -1131,6 +1131,8 @@ static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg
     goac_ctx* ctx = ch->ctx;
     const bool mixed = ch->prec == GOAC_MIXED;
     int wg = wg_req == 64 || wg_req == 256 ? wg_req : (ch->max_Mp >= 2048 ? 256 : 64);
+    // one-wave chains gather V_mm entries through 32-bit byte offsets
+    if ((uint64_t)ch->max_Mp * (uint64_t)ch->max_Mp * 8u >= ((uint64_t)1 << 32)) wg = 256;
     const size_t phi_bytes = (size_t)round_up(ch->max_Mp * (mixed ? 4 : 8), 16);
     const size_t lds = phi_bytes + (size_t)ch->max_Mp * (1 + 1 + 2 + 2) + round_up(ch->max_tab * 4, 16) +
                        kMaxSpecies * 8;

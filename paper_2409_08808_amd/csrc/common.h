@@ -311,8 +311,9 @@ goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, in
                         int64_t* idx64, int32_t* idx32, double* Eout);
 
 // kernels shared across translation units
+// C = alpha A B^T + beta C (FP64); sym: A = B and M = N, upper tiles computed and mirrored
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
-                     const int32_t* M_dev);
+                     const int32_t* M_dev, bool sym = false);
 
 }  // namespace goac

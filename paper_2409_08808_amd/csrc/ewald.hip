@@ -206,7 +206,7 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
         hipLaunchKernelGGL(k_ewald_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, n, K, ld,
                            d_pos, d_G, d_T);
         GOAC_CHECK_LAUNCH(ctx);
-        st = dgemm_nt(ctx, n, n, ld, d_T, ld, d_T, ld, V, n, 1.0, 1.0, nullptr);
+        st = dgemm_nt(ctx, n, n, ld, d_T, ld, d_T, ld, V, n, 1.0, 1.0, nullptr, true);
         if (st != GOAC_OK) return st;
     }
     // the uploads came from the staging ring, so the host vectors may go now

@@ -23,17 +23,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // on the current one (one barrier per slice). Rows beyond M (or *M_dev) and
 // columns beyond N are skipped; K is zero-padded. With split-K (gridDim.z > 1)
 // each z-slice writes its partial product to `part`, reduced in slice order by
-// k_dgemm_reduce (deterministic).
+// k_dgemm_reduce (deterministic). With sym (A = B, M = N: C += alpha A A^T), only
+// the tiles on and above the diagonal are computed; each mirrors its result into
+// the transposed tile (each element keeping its own beta C term).
 constexpr int DG_BM = 64, DG_BN = 64, DG_BK = 16;
+static_assert(DG_BM == DG_BN, "the symmetric product mirrors square tiles");
 
 __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                                   int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                   double* __restrict__ C, int64_t ldc, double alpha, double beta,
                                                   const int32_t* __restrict__ M_dev, int64_t k_per_split,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, int32_t sym) {
     __shared__ double As[2][DG_BK][DG_BM + 2];
     __shared__ double Bs[2][DG_BK][DG_BN + 2];
     if (M_dev) M = *M_dev;
+    if (sym && blockIdx.y > blockIdx.x) return;
     const int64_t m0 = (int64_t)blockIdx.y * DG_BM;
     const int64_t n0 = (int64_t)blockIdx.x * DG_BN;
     if (m0 >= M) return;
@@ -100,6 +104,10 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t 
                         double* c = C + r * ldc + cix;
                         const double val = alpha * acc[a][b][v];
                         *c = (beta == 0.0) ? val : val + beta * *c;
+                        if (sym && blockIdx.y < blockIdx.x) {
+                            double* ct = C + cix * ldc + r;
+                            *ct = (beta == 0.0) ? val : val + beta * *ct;
+                        }
                     }
                 }
             }
@@ -107,12 +115,14 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t 
 
 // C = alpha sum_z part[z] + beta C, slices summed in order
 __global__ void k_dgemm_reduce(int64_t M, int64_t N, int32_t splits, const double* __restrict__ part,
-                               double* __restrict__ C, int64_t ldc, double alpha, double beta) {
+                               double* __restrict__ C, int64_t ldc, double alpha, double beta, int32_t sym) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t r = idx / N, c = idx - r * N;
+    // below the diagonal tiles, a symmetric product's partials sit transposed
+    const int64_t src = (sym && r / DG_BM > c / DG_BN) ? c * N + r : idx;
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + src];
     double* o = C + r * ldc + c;
     const double val = alpha * s;
     *o = (beta == 0.0) ? val : val + beta * *o;
@@ -120,9 +130,12 @@ __global__ void k_dgemm_reduce(int64_t M, int64_t N, int32_t splits, const doubl
 
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
-                     const int32_t* M_dev) {
+                     const int32_t* M_dev, bool sym) {
     if (M <= 0 || N <= 0) return GOAC_OK;
-    const int64_t tiles = ((N + DG_BN - 1) / DG_BN) * ((M + DG_BM - 1) / DG_BM);
+    if (sym && (M != N || A != B || lda != ldb || M_dev))
+        return fail(ctx, GOAC_EINVAL, "dgemm_nt: a symmetric product needs A = B and M = N");
+    const int64_t tn = (N + DG_BN - 1) / DG_BN;
+    const int64_t tiles = sym ? tn * (tn + 1) / 2 : tn * ((M + DG_BM - 1) / DG_BM);
     // split K when the tile grid leaves most compute units idle and K is long
     int splits = 1;
     const int64_t want = 2 * (int64_t)ctx->num_cus;
@@ -137,11 +150,11 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
     }
     dim3 grid((unsigned)((N + DG_BN - 1) / DG_BN), (unsigned)((M + DG_BM - 1) / DG_BM), (unsigned)splits);
     hipLaunchKernelGGL(k_dgemm_nt, grid, dim3(256), 0, ctx->stream, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta,
-                       M_dev, kps, part);
+                       M_dev, kps, part, sym ? 1 : 0);
     GOAC_CHECK_LAUNCH(ctx);
     if (splits > 1) {
         hipLaunchKernelGGL(k_dgemm_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, ctx->stream, M, N,
-                           splits, part, C, ldc, alpha, beta);
+                           splits, part, C, ldc, alpha, beta, sym ? 1 : 0);
         GOAC_CHECK_LAUNCH(ctx);
     }
     return GOAC_OK;
@@ -376,12 +389,14 @@ __global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t 
     *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
 }
 
-// The same for rows of at most kDqStageMax sites: one workgroup per row reads the
-// row into LDS with coalesced 16-byte loads, then gathers from LDS. It also forms
-// the row's linear term lin[p] = sum_k dQ[p][k] ht[k] in FP64 (each thread sums its
-// k in order, then a fixed butterfly and the four waves in order).
+// The same for rows of at most kDqStageMax sites: one workgroup takes R rows, reads
+// them into LDS with coalesced 16-byte loads and gathers from LDS, reading the
+// position tables (site, sublattice, h~) once for the R rows. It also forms each
+// row's linear term lin[p] = sum_k dQ[p][k] ht[k] in FP64 (each thread sums its k
+// in order, then a fixed butterfly and the four waves in order).
 constexpr int64_t kDqStageMax = 48 * 1024;
 
+template <int R>
 __global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E,
                                                          const uint8_t* __restrict__ occ,
                                                          const int32_t* __restrict__ mob,
@@ -390,42 +405,73 @@ __global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, i
                                                          const double* __restrict__ ht,
                                                          __hip_bfloat16* __restrict__ out,
                                                          double* __restrict__ lin) {
-    extern __shared__ __align__(16) uint8_t row[];
-    __shared__ double wsum[4];
-    const int64_t p = blockIdx.x;
-    const uint8_t* src = occ + p * n;
-    // rows start at p * n bytes: 16-byte loads only when that is aligned
-    if ((((uintptr_t)src) & 15) == 0) {
-        for (int64_t x = threadIdx.x * 16; x < n; x += 256 * 16) {
-            if (x + 16 <= n) *reinterpret_cast<uint4*>(row + x) = *reinterpret_cast<const uint4*>(src + x);
-            else
-                for (int64_t y = x; y < n; ++y) row[y] = src[y];
+    extern __shared__ __align__(16) uint8_t rows[];
+    __shared__ double wsum[R][4];
+    const int64_t p0 = (int64_t)blockIdx.x * R;
+    const int64_t ld = round_up(n, 16);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = p0 + r;
+        if (p >= P) break;
+        const uint8_t* src = occ + p * n;
+        uint8_t* row = rows + r * ld;
+        // rows start at p * n bytes: 16-byte loads only when that is aligned
+        if ((((uintptr_t)src) & 15) == 0) {
+            for (int64_t x = threadIdx.x * 16; x < n; x += 256 * 16) {
+                if (x + 16 <= n) *reinterpret_cast<uint4*>(row + x) = *reinterpret_cast<const uint4*>(src + x);
+                else
+                    for (int64_t y = x; y < n; ++y) row[y] = src[y];
+            }
+        } else {
+            for (int64_t x = threadIdx.x; x < n; x += 256) row[x] = src[x];
         }
-    } else {
-        for (int64_t x = threadIdx.x; x < n; x += 256) row[x] = src[x];
     }
     __syncthreads();
-    double acc = 0.0;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
     for (int k0 = threadIdx.x * 8; k0 < Mp; k0 += 256 * 8) {
-        __hip_bfloat16 v[8];
+        // the position tables are read once for the R rows
+        int site[8], sub[8];
+        double h[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = k0 + q;
-            double x = 0.0;
-            if (k < M) {
-                const int e = row[mob[k]];
-                x = dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
-                acc += x * ht[k];
-            }
-            v[q] = __float2bfloat16((float)x);
+            site[q] = k < M ? mob[k] : 0;
+            sub[q] = k < M ? msub[k] : 0;
+            h[q] = k < M ? ht[k] : 0.0;
         }
-        *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = p0 + r;
+            if (p >= P) break;
+            const uint8_t* row = rows + r * ld;
+            __hip_bfloat16 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = k0 + q;
+                double x = 0.0;
+                if (k < M) {
+                    const int e = row[site[q]];
+                    x = dq[sub[q] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+                    acc[r] += x * h[q];
+                }
+                v[q] = __float2bfloat16((float)x);
+            }
+            *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
+        }
     }
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    for (int r = 0; r < R; ++r) {
+        double a = acc[r];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+        if ((threadIdx.x & 63) == 0) wsum[r][threadIdx.x >> 6] = a;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) lin[p] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (threadIdx.x < R && p0 + threadIdx.x < P)
+        lin[p0 + threadIdx.x] = ((wsum[threadIdx.x][0] + wsum[threadIdx.x][1]) + wsum[threadIdx.x][2]) +
+                                wsum[threadIdx.x][3];
 }
 
 // Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
@@ -519,8 +565,20 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
     double* lin = nullptr;
     if (d.n <= kDqStageMax) {
         lin = (double*)((char*)ws + dq_bytes + part_bytes);
-        hipLaunchKernelGGL(k_build_dq_staged, dim3((unsigned)P), dim3(256), round_up(d.n, 16), ctx->stream, P, d.n,
-                           d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+        // rows per workgroup: the position tables are read once for all of them
+        const int64_t ld = round_up(d.n, 16);
+        const int R = (P >= 4 * 2 * (int64_t)ctx->num_cus && 4 * ld <= 64 * 1024) ? 4
+                      : (P >= 2 * 2 * (int64_t)ctx->num_cus && 2 * ld <= 64 * 1024) ? 2 : 1;
+        const unsigned g = (unsigned)((P + R - 1) / R);
+        if (R == 4)
+            hipLaunchKernelGGL(k_build_dq_staged<4>, dim3(g), dim3(256), 4 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+        else if (R == 2)
+            hipLaunchKernelGGL(k_build_dq_staged<2>, dim3(g), dim3(256), 2 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+        else
+            hipLaunchKernelGGL(k_build_dq_staged<1>, dim3(g), dim3(256), ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
     } else
         hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream,
                            P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);

@@ -93,6 +93,26 @@ constexpr double kMargin = 1e-8;      // eV: covers the reference FP64 chain's o
 // absolute 2^-20 kT32 covers the log near u = 1. Trials with ub < 2 always stop.
 constexpr float kLn2Up = 0x1.62e448p-1f;  // >= ln 2 (1 + 2^-20)
 constexpr float kLn2Dn = 0x1.62e418p-1f;  // <= ln 2 (1 - 2^-20)
+// a uniform pointer held in scalar registers
+template <typename P>
+__device__ __forceinline__ P* sptr(P* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (P*)(((uint64_t)hi << 32) | lo);
+}
+
+// element x of a global array; with OFF32 through a 32-bit byte offset (arrays
+// below 4 GiB, which the host guarantees for one-wave chains)
+template <bool OFF32, typename T>
+__device__ __forceinline__ T gather(const GOAC_GLOBAL T* base, uint32_t x) {
+    if constexpr (OFF32)
+        return *reinterpret_cast<const GOAC_GLOBAL T*>(reinterpret_cast<const GOAC_GLOBAL char*>(base) +
+                                                       (uint32_t)(x * (uint32_t)sizeof(T)));
+    else
+        return base[(uint64_t)x];
+}
+
 // kT of the filter in FP32; below 2^-100 the bounds could lose their range, so the
 // filter then passes every trial to the exact rule
 __device__ __forceinline__ float kt_filter(double kT) { return kT >= 0x1p-100 ? (float)kT : INFINITY; }
@@ -155,6 +175,10 @@ template <bool MIXED, int WG, bool TRACE>
 __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int NW = WG / 64;
+    // several waves per chain (large cells, where accepted trials are frequent and
+    // a window's scoring costs the most) go on within a window after an accepted
+    // trial; one-wave chains start the next window instead (fewer live registers)
+    constexpr bool INWIN = NW > 1;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int s_item;
     __shared__ int s_first[2][NW];
@@ -196,9 +220,10 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         GOAC_GLOBAL uint8_t* gocc = gptr_rw(a.occ + off);
         GOAC_GLOBAL uint16_t* gperm = gptr_rw(a.perm + off);
         GOAC_GLOBAL uint8_t* gbest = gptr_rw(a.best + off);
-        const GOAC_GLOBAL double* V64 = gptr(I.V64);
-        const GOAC_GLOBAL float* V32 = gptr(I.V32);
-        const GOAC_GLOBAL double* diag = gptr(I.diag);
+        // the per-trial gathers take their bases from scalar registers
+        const GOAC_GLOBAL double* V64 = gptr(sptr(I.V64));
+        const GOAC_GLOBAL float* V32 = gptr(sptr(I.V32));
+        const GOAC_GLOBAL double* diag = gptr(sptr(I.diag));
         const GOAC_GLOBAL float* rowmax = gptr(I.rowmax);
         const GOAC_GLOBAL double* hv = gptr(I.h);
         const int ntab = tab_words(S, E);
@@ -254,7 +279,6 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         while (t < t_end) {
             const uint64_t left = t_end - t;
             const int nvalid = left < (uint64_t)WG ? (int)left : WG;
-            const uint64_t tl = t + (uint64_t)tid;
             // lanes from `split` on lie in block blk0 + 1
             int split = WG;
             float kTf;
@@ -270,211 +294,244 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 split = rel < (uint64_t)WG ? (int)rel : WG;
                 kTf = tid < split ? kTf0 : kTf1;
             } else {
-                const uint64_t blk = tl / a.block_len;
+                const uint64_t blk = (t + (uint64_t)tid) / a.block_len;
                 kTf = kt_filter(kTrow[blk < nb1 ? blk : nb1]);
             }
-            const u32x4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), chain_id, w3, a.seed);
-            const int i = (int)mulshift(r.x, (uint32_t)M);
-            // the loads that need only i go out first
-            const double Vii = diag[i];
-            const double phi_i = (double)phi[i];
-            const int s = S == 1 ? 0 : msub[i];
-            const int sa = occ[i];
-            const double qa = chg[sa];
-            // s < 16, E < 256, positions < 2^16: 24-bit products run at the full
-            // vector rate (32-bit integer products run at a quarter of it)
-            const int se = (int)__umul24((unsigned)s, (unsigned)E) + sa;
-            const int na = cnt[se];
-            const int csz = subsize[s] - na;
-            // scored without a branch: with csz == 0 the pick reads an in-range slot
-            // (perm is followed by where in LDS) and j falls back to i; such lanes and
-            // lanes past the end never stop
-            const int k = (int)mulshift(r.y, (uint32_t)csz);
-            const int idx = k < offs[se] ? k : k + na;
-            const int jp = perm[suboff[s] + idx];
-            const int j = csz > 0 ? jp : i;
-            const double Vjj = diag[j];
-            const double Vij = V64[__umul24((unsigned)i, (unsigned)Mp) + (unsigned)j];
-            const double phi_j = (double)phi[j];
-            const int sb = occ[j];
-            const double d = chg[sb] - qa;
-            const double dE = d * (phi_i - phi_j) + 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
-            // Metropolis threshold L = -kT ln u: an FP32 upper bound thr >= L from the
-            // top 24 bits of u (metropolis_band); a trial is surely rejected when
-            // dE - e > thr, e bounding the FP32 field's error in dE (MIXED). Every
-            // other trial stops the window and the first of them is resolved below.
+            const u32x4 r = [&] {
+                const uint64_t tl = t + (uint64_t)tid;
+                return philox((uint32_t)tl, (uint32_t)(tl >> 32), chain_id, w3, a.seed);
+            }();
+            // Metropolis threshold L = -kT ln u: FP32 bounds lo <= L <= thr from the
+            // top 24 bits of u (metropolis_band); trials with ub < 2 always stop
             const uint32_t ub = r.z >> 8;
-            float lg2, b;
-            metropolis_band(ub, lg2, b);
-            const double thr = (double)(kTf * fmaf(-lg2, kLn2Up, b));
-            double e = 0.0;
-            if constexpr (MIXED) e = fma(fabs(d), eps2, kMargin);
-            const bool stop = tid < nvalid && csz > 0 && (ub < 2 || !(dE - e > thr));
-            // first trial of the window that may be accepted
-            const uint64_t mask = __ballot(stop);
-            int f;
-            if (NW == 1) {
-                f = mask ? (int)__ffsll((long long)mask) - 1 : WG;
-            } else {
-                if (lane == 0) s_first[parity][wave] = mask ? wave * 64 + (int)__ffsll((long long)mask) - 1 : WG;
-                __syncthreads();
-                f = WG;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) f = min(f, s_first[parity][q]);
-                parity ^= 1;
+            float thr, lo;
+            {
+                float lg2, b;
+                metropolis_band(ub, lg2, b);
+                thr = kTf * fmaf(-lg2, kLn2Up, b);
+                lo = (ub >= 2 && kTf < INFINITY) ? kTf * fmaf(-lg2, kLn2Dn, -b) : -INFINITY;
             }
-            if (TRACE && tid < nvalid && tid < f) hsum += trial_hash(tl, (uint32_t)i, (uint32_t)j, 0u);
-            if (f >= nvalid) {
-                t += (uint64_t)nvalid;
-                while (t >= bnd) { ++blk0; bnd += a.block_len; }
-                continue;
-            }
-            if (tid == f) {
-                double kT;
-                if (wide_blocks) {
-                    kT = f < split ? kT0 : kT1;
+            // the trial's swap (i, j) against the current state: d = q_j - q_i and
+            // dE = d (phi_i - phi_j) + quad, quad = 1/2 d^2 (V_ii + V_jj - 2 V_ij).
+            // Scored without a branch: with csz == 0 the pick reads an in-range slot
+            // (perm is followed by where in LDS) and j falls back to i; such lanes and
+            // lanes past the end never stop.
+            int i, j, csz;
+            double d, quad, dE;
+            auto score = [&]() {
+                i = (int)mulshift(r.x, (uint32_t)M);
+                // the loads that need only i go out first
+                const double Vii = gather<WG == 64>(diag, (uint32_t)i);
+                const double phi_i = (double)phi[i];
+                const int s = S == 1 ? 0 : msub[i];
+                const int sa = occ[i];
+                const double qa = chg[sa];
+                // s < 16, E < 256, positions < 2^16: 24-bit products run at the full
+                // vector rate (32-bit integer products run at a quarter of it)
+                const int se = (int)__umul24((unsigned)s, (unsigned)E) + sa;
+                const int na = cnt[se];
+                csz = subsize[s] - na;
+                const int k = (int)mulshift(r.y, (uint32_t)csz);
+                const int idx = k < offs[se] ? k : k + na;
+                const int jp = perm[suboff[s] + idx];
+                j = csz > 0 ? jp : i;
+                const double Vjj = gather<WG == 64>(diag, (uint32_t)j);
+                const double Vij = gather<WG == 64>(V64, __umul24((unsigned)i, (unsigned)Mp) + (unsigned)j);
+                const double phi_j = (double)phi[j];
+                const int sb = occ[j];
+                d = chg[sb] - qa;
+                quad = 0.5 * d * d * (Vii + Vjj - 2.0 * Vij);
+                dE = d * (phi_i - phi_j) + quad;
+            };
+            score();
+            // The window's trials are decided in order: every trial before the first
+            // one that may be accepted is rejected; that one is resolved and, when
+            // accepted, applied. INWIN then scores the trials after it again against
+            // the new state (their draws are unchanged) and goes on within the window;
+            // otherwise the next window starts after it. A trial is surely rejected
+            // when dE - e > thr, e bounding the FP32 field's error in dE (MIXED).
+            int from = 0, used = nvalid;
+            for (;;) {
+                double e = 0.0;
+                if constexpr (MIXED) e = fma(fabs(d), eps2, kMargin);
+                const bool stop = tid >= from && tid < nvalid && csz > 0 && (ub < 2 || !(dE - e > (double)thr));
+                const uint64_t mask = __ballot(stop);
+                int f;
+                if (NW == 1) {
+                    f = mask ? (int)__ffsll((long long)mask) - 1 : WG;
                 } else {
-                    const uint64_t blk = tl / a.block_len;
-                    kT = kTrow[blk < nb1 ? blk : nb1];
+                    if (lane == 0) s_first[parity][wave] = mask ? wave * 64 + (int)__ffsll((long long)mask) - 1 : WG;
+                    __syncthreads();
+                    f = WG;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) f = min(f, s_first[parity][q]);
+                    parity ^= 1;
                 }
-                // sure accept: even dE + e lies below the lower bound of L
-                const double lo = (double)(kTf * fmaf(-lg2, kLn2Dn, -b));
-                const bool sure = d == 0.0 || dE + e <= 0.0 || (ub >= 2 && kTf < INFINITY && dE + e < lo);
-                s_b.i = i; s_b.j = j; s_b.unsure = sure ? 0 : 1;
-                s_b.d = d; s_b.dE = dE; s_b.u = unit_open(r.z, r.w); s_b.kT = kT;
-            }
-            __syncthreads();
-            const int bi = s_b.i, bj = s_b.j;
-            const double bd = s_b.d;
-            double bdE = s_b.dE;
-            bool accf = true;
-            if (s_b.unsure) {
-                if constexpr (MIXED) {
-                    // exact FP64 difference phi_i - phi_j from the occupation
-                    double part = 0.0;
-                    for (int k = tid; k < M; k += WG)
-                        part += (V64[(int64_t)bi * Mp + k] - V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
-                    const double diff = wg_sum<WG>(part, s_scr) + (hv[bi] - hv[bj]);
-                    const double Vii = diag[bi], Vjj = diag[bj];
-                    const double Vij = V64[(int64_t)bi * Mp + bj];
-                    bdE = bd * diff + 0.5 * bd * bd * (Vii + Vjj - 2.0 * Vij);
-                    ++n_fb;
-                }
-                // the exact rule (the FP64 field's dE is exact already)
-                accf = (bdE <= 0.0) || (s_b.u < exp(-bdE / s_b.kT));
-            }
-            if (TRACE && tid == f) hsum += trial_hash(tl, (uint32_t)bi, (uint32_t)bj, accf ? 1u : 0u);
-            if (accf) {
-                bool grew = false;   // MIXED: some |phi'| passed phib
-                if (bd != 0.0) {
-                    const T dd = (T)bd;
-                    const GOAC_GLOBAL T* Vi;
-                    const GOAC_GLOBAL T* Vj;
-                    if constexpr (MIXED) {
-                        Vi = V32 + (int64_t)bi * Mp;
-                        Vj = V32 + (int64_t)bj * Mp;
+                if (TRACE && tid >= from && tid < nvalid && tid < f)
+                    hsum += trial_hash(t + (uint64_t)tid, (uint32_t)i, (uint32_t)j, 0u);
+                if (f >= nvalid) break;
+                if (tid == f) {
+                    double kT;
+                    if (wide_blocks) {
+                        kT = f < split ? kT0 : kT1;
                     } else {
-                        Vi = V64 + (int64_t)bi * Mp;
-                        Vj = V64 + (int64_t)bj * Mp;
+                        const uint64_t blk = (t + (uint64_t)tid) / a.block_len;
+                        kT = kTrow[blk < nb1 ? blk : nb1];
                     }
-                    bool over = false;
-                    // rows i and j streamed as 16-byte vectors, U vectors per thread in
-                    // flight before the field is touched
-                    constexpr int VEC = MIXED ? 4 : 2;
-                    constexpr int U = WG >= 256 ? 8 : 1;   // one wave per chain: keep registers low
-                    typedef float f32x4v __attribute__((ext_vector_type(4)));
-                    typedef double f64x2v __attribute__((ext_vector_type(2)));
-                    using V16 = typename std::conditional<MIXED, f32x4v, f64x2v>::type;
-                    const GOAC_GLOBAL V16* Vi16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vi);
-                    const GOAC_GLOBAL V16* Vj16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vj);
-                    const int nv = Mp / VEC;
-                    for (int v0 = tid; v0 < nv; v0 += WG * U) {
-                        V16 a[U], b[U];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int v = v0 + u * WG;
-                            if (v < nv) {
-                                a[u] = Vi16[v];
-                                b[u] = Vj16[v];
-                            }
+                    // sure accept: even dE + e lies below the lower bound of L
+                    const bool sure = d == 0.0 || dE + e <= 0.0 || dE + e < (double)lo;
+                    s_b.i = i; s_b.j = j; s_b.unsure = sure ? 0 : 1;
+                    s_b.d = d; s_b.dE = dE; s_b.u = unit_open(r.z, r.w); s_b.kT = kT;
+                }
+                __syncthreads();
+                const int bi = s_b.i, bj = s_b.j;
+                const double bd = s_b.d;
+                double bdE = s_b.dE;
+                bool accf = true;
+                if (s_b.unsure) {
+                    if constexpr (MIXED) {
+                        // exact FP64 difference phi_i - phi_j from the occupation
+                        double part = 0.0;
+                        for (int k = tid; k < M; k += WG)
+                            part += (V64[(int64_t)bi * Mp + k] - V64[(int64_t)bj * Mp + k]) * chg[occ[k]];
+                        const double diff = wg_sum<WG>(part, s_scr) + (hv[bi] - hv[bj]);
+                        const double Vii = diag[bi], Vjj = diag[bj];
+                        const double Vij = V64[(int64_t)bi * Mp + bj];
+                        bdE = bd * diff + 0.5 * bd * bd * (Vii + Vjj - 2.0 * Vij);
+                        ++n_fb;
+                    }
+                    // the exact rule (the FP64 field's dE is exact already)
+                    accf = (bdE <= 0.0) || (s_b.u < exp(-bdE / s_b.kT));
+                }
+                if (TRACE && tid == f) hsum += trial_hash(t + (uint64_t)tid, (uint32_t)bi, (uint32_t)bj, accf ? 1u : 0u);
+                if (accf) {
+                    bool grew = false;   // MIXED: some |phi'| passed phib
+                    if (bd != 0.0) {
+                        const T dd = (T)bd;
+                        const GOAC_GLOBAL T* Vi;
+                        const GOAC_GLOBAL T* Vj;
+                        if constexpr (MIXED) {
+                            Vi = V32 + (int64_t)bi * Mp;
+                            Vj = V32 + (int64_t)bj * Mp;
+                        } else {
+                            Vi = V64 + (int64_t)bi * Mp;
+                            Vj = V64 + (int64_t)bj * Mp;
                         }
+                        bool over = false;
+                        // rows i and j streamed as 16-byte vectors, U vectors per thread in
+                        // flight before the field is touched
+                        constexpr int VEC = MIXED ? 4 : 2;
+                        constexpr int U = WG >= 256 ? 8 : 1;   // one wave per chain: keep registers low
+                        typedef float f32x4v __attribute__((ext_vector_type(4)));
+                        typedef double f64x2v __attribute__((ext_vector_type(2)));
+                        using V16 = typename std::conditional<MIXED, f32x4v, f64x2v>::type;
+                        const GOAC_GLOBAL V16* Vi16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vi);
+                        const GOAC_GLOBAL V16* Vj16 = reinterpret_cast<const GOAC_GLOBAL V16*>(Vj);
+                        const int nv = Mp / VEC;
+                        for (int v0 = tid; v0 < nv; v0 += WG * U) {
+                            V16 av4[U], bv4[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int v = v0 + u * WG;
-                            if (v < nv) {
-                                const T* av = reinterpret_cast<const T*>(&a[u]);
-                                const T* bv = reinterpret_cast<const T*>(&b[u]);
+                            for (int u = 0; u < U; ++u) {
+                                const int v = v0 + u * WG;
+                                if (v < nv) {
+                                    av4[u] = Vi16[v];
+                                    bv4[u] = Vj16[v];
+                                }
+                            }
 #pragma unroll
-                                for (int q = 0; q < VEC; ++q) {
-                                    const int k = v * VEC + q;
-                                    T p = phi[k];
-                                    if constexpr (MIXED) {
-                                        p = fmaf(dd, av[q], p);
-                                        p = fmaf(-dd, bv[q], p);
-                                        over |= fabsf(p) > phib;
-                                    } else {
-                                        p = p + dd * (av[q] - bv[q]);
+                            for (int u = 0; u < U; ++u) {
+                                const int v = v0 + u * WG;
+                                if (v < nv) {
+                                    const T* av = reinterpret_cast<const T*>(&av4[u]);
+                                    const T* bv = reinterpret_cast<const T*>(&bv4[u]);
+#pragma unroll
+                                    for (int q = 0; q < VEC; ++q) {
+                                        const int k = v * VEC + q;
+                                        T p = phi[k];
+                                        if constexpr (MIXED) {
+                                            p = fmaf(dd, av[q], p);
+                                            p = fmaf(-dd, bv[q], p);
+                                            over |= fabsf(p) > phib;
+                                        } else {
+                                            p = p + dd * (av[q] - bv[q]);
+                                        }
+                                        phi[k] = p;
                                     }
-                                    phi[k] = p;
                                 }
                             }
                         }
+                        if constexpr (MIXED) {
+                            if constexpr (NW == 1) grew = __ballot(over) != 0;
+                            else if (over) s_flag = 1;
+                        }
+                        ++n_upd;
+                        ++since;
                     }
-                    if constexpr (MIXED) {
-                        if constexpr (NW == 1) grew = __ballot(over) != 0;
-                        else if (over) s_flag = 1;
+                    if (tid == 0) {
+                        const uint8_t sa = occ[bi], sb = occ[bj];
+                        occ[bi] = sb;
+                        occ[bj] = sa;
+                        const uint16_t wi = where[bi], wj = where[bj];
+                        perm[wi] = (uint16_t)bj;
+                        perm[wj] = (uint16_t)bi;
+                        where[bi] = wj;
+                        where[bj] = wi;
                     }
-                    ++n_upd;
-                    ++since;
-                }
-                if (tid == 0) {
-                    const uint8_t sa = occ[bi], sb = occ[bj];
-                    occ[bi] = sb;
-                    occ[bj] = sa;
-                    const uint16_t wi = where[bi], wj = where[bj];
-                    perm[wi] = (uint16_t)bj;
-                    perm[wj] = (uint16_t)bi;
-                    where[bi] = wj;
-                    where[bj] = wi;
-                }
-                Ecur += bdE;
-                ++n_acc;
-                __syncthreads();
-                if constexpr (MIXED) if (bd != 0.0) {
-                    if constexpr (NW > 1) grew = s_flag != 0;
-                    if (grew) {
-                        // |phi'| grew past the bound: take the exact maximum
-                        double pm = 0.0;
-                        for (int k = tid; k < M; k += WG) pm = fmax(pm, fabs((double)phi[k]));
-                        pm = wg_max<WG>(pm, s_scr);
-                        float pb = phib;
-                        while ((double)pb < 2.0 * pm) pb *= 2.0f;
-                        phib = pb;
-                        if constexpr (NW > 1) {
+                    Ecur += bdE;
+                    ++n_acc;
+                    __syncthreads();
+                    if constexpr (MIXED) if (bd != 0.0) {
+                        if constexpr (NW > 1) grew = s_flag != 0;
+                        if (grew) {
+                            // |phi'| grew past the bound: take the exact maximum
+                            double pm = 0.0;
+                            for (int k = tid; k < M; k += WG) pm = fmax(pm, fabs((double)phi[k]));
+                            pm = wg_max<WG>(pm, s_scr);
+                            float pb = phib;
+                            while ((double)pb < 2.0 * pm) pb *= 2.0f;
+                            phib = pb;
+                            if constexpr (NW > 1) {
+                                __syncthreads();
+                                if (tid == 0) s_flag = 0;
+                            }
+                        }
+                        // two fused multiply-adds per element, each rounding <= u |intermediate|,
+                        // plus the FP32 rounding of the two V entries (rows bounded by rmax)
+                        eps += kU32 * (2.0 * (double)phib + fabs(bd) * (5.0 * rmax)) * 1.0001;
+                        if (!(eps < 1e3)) status = 1;
+                        if (a.inline_anchor && since >= (uint32_t)a.reanchor_every) {
                             __syncthreads();
-                            if (tid == 0) s_flag = 0;
+                            anchor_chain<WG>(I, occ, msub, chg, s_phibar, reinterpret_cast<float*>(phi), s_scr,
+                                             Ecur, eps, phib);
+                            since = 0;
+                            ++n_anc;
+                            __syncthreads();
+                        }
+                        eps2 = 2.0 * eps;
+                    }
+                    if (Ecur < best) {
+                        best = Ecur;
+                        for (int k = tid; k < Mp; k += WG) gbest[k] = occ[k];
+                    }
+                    // the trials after f against the new state: a trial touching i or j
+                    // (its species, its partner list) is scored afresh, the others only
+                    // take the new field
+                    if constexpr (INWIN) {
+                        if (tid > f && tid < nvalid) {
+                            if (i == bi || i == bj || j == bi || j == bj)
+                                score();
+                            else
+                                dE = d * ((double)phi[i] - (double)phi[j]) + quad;
                         }
                     }
-                    // two fused multiply-adds per element, each rounding <= u |intermediate|,
-                    // plus the FP32 rounding of the two V entries (rows bounded by rmax)
-                    eps += kU32 * (2.0 * (double)phib + fabs(bd) * (5.0 * rmax)) * 1.0001;
-                    if (!(eps < 1e3)) status = 1;
-                    if (a.inline_anchor && since >= (uint32_t)a.reanchor_every) {
-                        __syncthreads();
-                        anchor_chain<WG>(I, occ, msub, chg, s_phibar, reinterpret_cast<float*>(phi), s_scr, Ecur,
-                                         eps, phib);
-                        since = 0;
-                        ++n_anc;
-                        __syncthreads();
-                    }
-                    eps2 = 2.0 * eps;
                 }
-                if (Ecur < best) {
-                    best = Ecur;
-                    for (int k = tid; k < Mp; k += WG) gbest[k] = occ[k];
+                if constexpr (!INWIN) {
+                    used = f + 1;
+                    break;
                 }
+                from = f + 1;
             }
-            t += (uint64_t)(f + 1);
+            t += (uint64_t)used;
             while (t >= bnd) { ++blk0; bnd += a.block_len; }
         }
         // ---- write the chain back
