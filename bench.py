@@ -229,7 +229,9 @@ def ga_energies(ctx, G, S, torch, stream, generations):
         out["ga_%s_energy_call_us" % name] = 1e6 * t_en / gens
         out["ga_%s_generation_ms" % name] = 1e3 * wall / gens
         if prec == G.GOAC_MIXED:
-            flops = 2 * 2.0 * 1024 * 2048 * 2048
+            # the symmetric product forms the upper triangle of the (k, n) plane, hi
+            # and lo: 2 x 2 x P x M (M + 1) / 2 flops per call
+            flops = 2 * 2.0 * 1024 * 2048 * 2049 / 2
             out["ga_mixed_mfma_frac"] = flops / (t_en / gens) / BF16_PEAK
     out["energies_per_s"] = out["ga_mixed_energies_per_s"]
     pb.close()

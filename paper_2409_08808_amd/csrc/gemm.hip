@@ -161,10 +161,15 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 }
 
 // ------------------------------------------------------------------ bf16 hi+lo population GEMM
-// Phi[p][n] = sum_k dQ[p][k] (Vhi[n][k] + Vlo[n][k]) (V is symmetric, so its rows
+// E_p - lin_p - E~ = 1/2 dQ_p^T V dQ_p with V = Vhi + Vlo symmetric (so its rows
 // serve as columns), bf16 inputs, FP32 accumulation on v_mfma_f32_32x32x16_bf16.
-// Fused epilogue per output tile (linear in Phi, so K may be split):
-//   part[t][p] = 1/2 sum_{n in tile} dQ[p][n] Phi_slice[p][n]
+// The (k, n) plane is cut into blocks of KB = KT n-tiles each way; with
+// T_ij = sum_{k in block i, n in block j} dQ[p][k] V[k][n] dQ[p][n] and T_ij = T_ji,
+//   1/2 dQ^T V dQ = sum_i 1/2 T_ii + sum_{i<j} T_ij,
+// so only the blocks with i <= j are formed (about half the matrix work and the
+// V traffic). A workgroup takes one p-tile, one n-tile of block j and the K range
+// of block i, and its fused epilogue writes
+//   part[t][p] = w sum_{n in tile} dQ[p][n] Phi_slice[p][n],  w = 1/2 (i = j), 1 (i < j)
 // in FP32 within the tile (dQ is a small integer; the error stays orders of
 // magnitude below the FP32 accumulation of Phi itself) and FP64 across tiles. The
 // linear term dQ . ht is added in FP64 by k_pop_finalize.
@@ -173,35 +178,17 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 // operand reads (the hi/lo pair doubles the n-side operand, so the wave tile is
 // long in p). The next K stage is fetched into registers while the matrix cores
 // work on the current one; double-buffered LDS (80 KiB, two workgroups per
-// compute unit), one barrier per stage.
-//
-// Workgroup order. Each XCD has its own L2, and workgroups are dealt to the XCDs
-// round-robin. Order 0 decodes the linear id as (n-tile, p-tile, K-slice) with
-// the K-slice fastest, so the K-slices of a tile land on different XCDs and an
-// XCD streams one K range of every operand; order 1 first gives each XCD a
-// contiguous block of linear ids, so it streams a few column tiles over all K.
-// The host picks the order with the smaller largest per-XCD working set.
+// compute unit), one barrier per stage. Workgroup id -> (p-tile fastest, then the
+// (n-tile, K block) pairs in n-tile order, n-tile t having t / KT + 1 of them).
 constexpr int PB_BM = 256, PB_BN = 128, PB_BK = 32, PB_LD = PB_BK + 8, PB_DLD = PB_BN + 8;
 constexpr int kPopLds = 2 * (PB_BM + 2 * PB_BN) * PB_LD * 2;   // 80 KiB
 static_assert(PB_BM * PB_DLD * 2 + PB_BM * 2 * 8 <= kPopLds, "epilogue staging exceeds the stage buffers");
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ void pop_tile_of(int order, int id, int MT, int S, int total, int& mt, int& nt,
-                                            int& split) {
-    int u = id;
-    if (order == 1) u = (id % kXcds) * (total / kXcds) + id / kXcds;
-    nt = u / (MT * S);
-    const int rem = u - nt * (MT * S);
-    mt = rem / S;
-    split = rem - mt * S;
-}
 
 __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32_t Mp,
                                                      const __hip_bfloat16* __restrict__ dQ,
                                                      const __hip_bfloat16* __restrict__ Vhi,
                                                      const __hip_bfloat16* __restrict__ Vlo,
-                                                     double* __restrict__ part, int32_t MT, int32_t S,
-                                                     int32_t k_per_split, int32_t order) {
+                                                     double* __restrict__ part, int32_t MT, int32_t KT) {
     // operand stages during the K loop; the epilogue reuses the same bytes for the
     // tile's dQ block and the row sums
     __shared__ __align__(16) unsigned char smem[kPopLds];
@@ -210,13 +197,20 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32
     auto Ls = reinterpret_cast<__hip_bfloat16 (*)[PB_BN][PB_LD]>(smem + 2 * (PB_BM + PB_BN) * PB_LD * 2);
     auto Ds = reinterpret_cast<__hip_bfloat16 (*)[PB_DLD]>(smem);
     auto red = reinterpret_cast<double (*)[2]>(smem + PB_BM * PB_DLD * 2);
-    const int total = (int)gridDim.x;
-    int mt, nt, split;
-    pop_tile_of(order, (int)blockIdx.x, MT, S, total, mt, nt, split);
+    const int u = (int)blockIdx.x;
+    const int mt = u % MT;
+    const int slot = u / MT;   // the (n-tile, K block) pair, also part's row
+    int pr = slot, nt = 0;
+    while (pr >= nt / KT + 1) {
+        pr -= nt / KT + 1;
+        ++nt;
+    }
+    const int kb_len = KT * PB_BN;
+    const int kbeg = pr * kb_len;
+    const double wgt = pr < nt / KT ? 1.0 : 0.5;
     const int64_t m0 = (int64_t)mt * PB_BM;
     const int n0 = nt * PB_BN;
-    const int kbeg = split * k_per_split;
-    const int kend = kbeg + k_per_split < Mp ? kbeg + k_per_split : Mp;
+    const int kend = kbeg + kb_len < Mp ? kbeg + kb_len : Mp;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -343,7 +337,7 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32
     }
     __syncthreads();
     const int64_t gp = m0 + tid;
-    if (gp < P) part[(int64_t)(nt * S + split) * P + gp] = 0.5 * (red[tid][0] + red[tid][1]);
+    if (gp < P) part[(int64_t)slot * P + gp] = wgt * (red[tid][0] + red[tid][1]);
 }
 
 // E[p] = E~ + lin[p] + sum over (column tile, K slice) t of part[t][p], with
@@ -516,45 +510,34 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
     return GOAC_OK;
 }
 
-// Largest number of distinct operand bytes one XCD streams under a workgroup order
-// (the p-rows and n-rows of every K slice its workgroups touch).
-static double pop_xcd_bytes(int order, int MT, int NT, int S, int kps) {
-    const int total = MT * NT * S;
-    double worst = 0.0;
-    for (int x = 0; x < kXcds; ++x) {
-        std::vector<char> a((size_t)MT * S, 0), b((size_t)NT * S, 0);
-        for (int id = x; id < total; id += kXcds) {
-            int u = id;
-            if (order == 1) u = (id % kXcds) * (total / kXcds) + id / kXcds;
-            const int nt = u / (MT * S), rem = u - nt * (MT * S), mt = rem / S, sp = rem - mt * S;
-            a[(size_t)mt * S + sp] = 1;
-            b[(size_t)nt * S + sp] = 1;
-        }
-        double bytes = 0.0;
-        for (char c : a) bytes += c ? (double)PB_BM * kps * 2 : 0.0;
-        for (char c : b) bytes += c ? (double)PB_BN * kps * 4 : 0.0;
-        worst = std::max(worst, bytes);
-    }
-    return worst;
-}
-
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
     const int64_t MT = (P + PB_BM - 1) / PB_BM;
-    if (MT * NT > (int64_t)1 << 24) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
-    // split K until the grid holds two workgroups per compute unit (the epilogue is
-    // linear in Phi), so that one workgroup's loads overlap the other's matrix work
-    int S = 1;
-    while (MT * NT * S < 2 * (int64_t)ctx->num_cus && d.Mp / (S * 2) >= 256 && S < 16) S *= 2;
-    const int32_t kps = (int32_t)round_up((d.Mp + S - 1) / S, PB_BK);
-    const int64_t total = MT * NT * S;
-    int order = 0;
-    if (total % kXcds == 0 && total <= (1 << 16) &&
-        pop_xcd_bytes(1, (int)MT, NT, S, kps) < pop_xcd_bytes(0, (int)MT, NT, S, kps))
-        order = 1;
-    const int32_t n_parts = NT * S;
+    // the symmetric form: K blocks of KT n-tiles; pairs(KT) = sum_t (t / KT + 1).
+    // KT minimises the estimated makespan: rounds of two workgroups per compute unit
+    // times the K length of one plus a fixed cost of 128 K steps (measured on the
+    // 4x4x4, 8x8x8 and 16x16x8 rock-salt populations); ties go to the longer K
+    auto pairs = [&](int kt) {
+        int64_t n = 0;
+        for (int t = 0; t < NT; ++t) n += t / kt + 1;
+        return n;
+    };
+    int KT = 1;
+    int64_t best_cost = -1;
+    for (int kt = 1; kt <= 8 && (kt == 1 || kt <= NT); kt *= 2) {
+        const int64_t wg = MT * pairs(kt);
+        const int64_t rounds = (wg + 2 * ctx->num_cus - 1) / (2 * ctx->num_cus);
+        const int64_t cost = rounds * ((int64_t)kt * PB_BN + 128);
+        if (best_cost < 0 || cost <= best_cost) {
+            best_cost = cost;
+            KT = kt;
+        }
+    }
+    const int64_t total = MT * pairs(KT);
+    if (total > ((int64_t)1 << 30)) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
+    const int32_t n_parts = (int32_t)pairs(KT);
     const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
     const size_t part_bytes = round_up((size_t)P * n_parts * sizeof(double), 256);
     void* ws = nullptr;
@@ -584,7 +567,7 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
                            P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)total), dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo,
-                       part, (int32_t)MT, S, kps, order);
+                       part, (int32_t)MT, KT);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
                        n_parts, dQ, d.ht, part, lin, d.Ed, E);

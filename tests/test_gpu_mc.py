@@ -106,6 +106,23 @@ def test_mc_config2_annealed(ctx, cfg2, prec, reanchor, variant):
         assert np.array_equal(stats["anchors"], stats["updates"] // reanchor)
 
 
+@pytest.mark.parametrize("which,kT", [("two", 5.0), ("two", 0.3), ("many", 0.1)])
+@pytest.mark.parametrize("prec,variant", [(0, 64), (0, 256), (1, 64), (1, 256)])
+def test_mc_frequent_accepts(ctx, which, kT, prec, variant):
+    """Windows with many accepted trials: two mobile site classes at high kT, and a
+    class whose species all carry the same charge (every swap has dE = 0 and is
+    accepted). Multi-wave chains (256 lanes) go on within a window after each
+    accepted swap, rescoring the later trials; one-wave chains start a new window.
+    Both must follow the sequential chain exactly."""
+    cell = two_sublattice_cell() if which == "two" else many_species_cell()
+    V = O.cell_matrix(cell)
+    occ0 = O.init_occupations(cell, 24, seed=5)
+    st = _run_oracle(cell, V, occ0, 3000, [kT], 10 ** 9, 5)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 3000, [kT], 10 ** 9, 5, reanchor=64, variant=variant)
+    _compare(cell, stats, occ, best, st, prec, V)
+    assert stats["accepts"].sum() > 0.01 * 24 * 3000
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_mc_resume(ctx, cfg2, prec):
     cell, V = cfg2
