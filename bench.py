@@ -37,9 +37,9 @@ BF16_PEAK = 2.5e15
 # HBM bytes of one k_mc<mixed, 64> launch of this step from FETCH_SIZE and WRITE_SIZE,
 # each scaled by the same counter's reading for a 256 MiB copy (factors 2.0 and 1.0);
 # valid only for the kernel sources they were taken on (profiles/k_mc_rocksalt4x4x4_traffic.md)
-MC_TRAFFIC = {"bytes": 61085427.0,
+MC_TRAFFIC = {"bytes": 55920387.0,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": "aaacf1f51a7c33caa8315c72722c749bcf1b3b25ec0ce9e91d2e5c0ce1d9a6d8"}
+              "sha256": "7fc172f2f61941b4767cee9bab73708ba71adb549e18968bf06740055b5f1fbb"}
 
 
 def parse():
