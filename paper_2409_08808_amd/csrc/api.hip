@@ -1134,8 +1134,10 @@ static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg
     // one-wave chains gather V_mm entries through 32-bit byte offsets
     if ((uint64_t)ch->max_Mp * (uint64_t)ch->max_Mp * 8u >= ((uint64_t)1 << 32)) wg = 256;
     const size_t phi_bytes = (size_t)round_up(ch->max_Mp * (mixed ? 4 : 8), 16);
-    const size_t lds = phi_bytes + (size_t)ch->max_Mp * (1 + 1 + 2 + 2) + round_up(ch->max_tab * 4, 16) +
-                       kMaxSpecies * 8;
+    // occupation, site class (only with several classes), perm and where per position
+    const bool msub_lds = ch->max_S > 1;
+    const size_t lds = phi_bytes + (size_t)ch->max_Mp * (1 + (msub_lds ? 1 : 0) + 2 + 2) +
+                       round_up(ch->max_tab * 4, 16) + kMaxSpecies * 8;
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "mc_sweep: the chain state does not fit in LDS");
     const int cap = std::max<int>(1, std::min<int>(wg == 64 ? 16 : 4, (int)((160 * 1024) / lds)));
     const int per_cu = per_cu_req > 0 ? std::min(per_cu_req, cap) : cap;
@@ -1166,7 +1168,7 @@ static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg
     // MIXED: small cells re-anchor inside the kernel; large cells run in chunks of
     // 8 x reanchor_every trials with a batched FP64 anchor of the due chains after each
     a.inline_anchor = (mixed && ch->max_Mp > kInlineAnchorMaxMp) ? 0 : 1;
-    a.pad_ = 0;
+    a.msub_lds = msub_lds ? 1 : 0;
     return GOAC_OK;
 }
 

@@ -286,7 +286,7 @@ struct McArgs {
     int32_t tab_max;       // int32 words reserved for tables
     int32_t inline_anchor; // MIXED: re-anchor inside the kernel (small cells) or leave it to
                            // the batched FP64 product between chunks (large cells)
-    int32_t pad_;
+    int32_t msub_lds;      // some instance has several site classes: their ids live in LDS
 };
 
 goac_status mc_launch(goac_ctx* ctx, const McArgs& a, bool mixed, bool trace, int wg, size_t lds, int grid);

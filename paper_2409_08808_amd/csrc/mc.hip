@@ -151,7 +151,7 @@ __device__ void anchor_chain(const McInst& I, const uint8_t* occ, const uint8_t*
             const double hk = hv[k];
             const double qk = chg[occ[k]];
             esum += qk * (acc + hk);
-            const float p = (float)(acc - phibar[msub[k]]);
+            const float p = (float)(acc - phibar[I.S == 1 ? 0 : msub[k]]);
             phi[k] = p;
             pmax = fmax(pmax, fabs((double)p));
             amax = fmax(amax, aab);
@@ -191,8 +191,9 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     const int lane = tid & 63, wave = tid >> 6;
     T* phi = reinterpret_cast<T*>(lds);
     uint8_t* occ = lds + a.lds_phi_bytes;
+    // site-class ids take LDS only when some instance has more than one class
     uint8_t* msub = occ + a.Mp_max;
-    uint16_t* perm = reinterpret_cast<uint16_t*>(msub + a.Mp_max);
+    uint16_t* perm = reinterpret_cast<uint16_t*>(msub + (a.msub_lds ? a.Mp_max : 0));
     uint16_t* where = perm + a.Mp_max;
     int32_t* tab = reinterpret_cast<int32_t*>(where + a.Mp_max);
     double* chg = reinterpret_cast<double*>(tab + a.tab_max);
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         for (int k = tid; k < Mp; k += WG) {
             phi[k] = gphi[k];
             occ[k] = gocc[k];
-            msub[k] = gptr(I.msub)[k];
+            if (S > 1) msub[k] = gptr(I.msub)[k];
             const uint16_t p = gperm[k];
             perm[k] = p;
         }
