@@ -282,7 +282,9 @@ def large_cell(ctx, G, S, torch, stream):
 
 def batched_instances(ctx, G, S, torch, stream):
     """512 rock-salt/spinel instances (N log-uniform in [64, 2048]), 256 chains each,
-    2e4 trials, kT 0.3 -> 0.01 eV over 20 blocks, one persistent launch (mixed)."""
+    2e4 trials, kT 0.3 -> 0.01 eV over 20 blocks, one persistent launch whose
+    workgroup size and chains per compute unit the autotuner picks (on a 2000-trial
+    probe that leaves the chains unchanged, not timed)."""
     cells = S.config4()
     t0 = time.perf_counter()
     pbs = []
@@ -297,6 +299,7 @@ def batched_instances(ctx, G, S, torch, stream):
     out = {}
     for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
         ch = G.Chains.batch(pbs, [256] * len(pbs), flat, prec)
+        out["cfg4_%s_autotune" % name] = list(ch.autotune(2000, 0.3))
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
