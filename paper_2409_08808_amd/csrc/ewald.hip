@@ -13,6 +13,8 @@
 // an FP64 matrix-core product added onto the real-space part.
 #include <cmath>
 
+#include <cstring>
+
 #include "common.h"
 
 namespace goac {
@@ -186,11 +188,14 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
             cpos[3 * i + k] = frac[3 * i] * c.A[0][k] + frac[3 * i + 1] * c.A[1][k] + frac[3 * i + 2] * c.A[2][k];
-    GOAC_TRY(upload(ctx, d_frac, frac.data(), frac.size() * 8));
-    GOAC_TRY(upload(ctx, d_pos, cpos.data(), cpos.size() * 8));
-    GOAC_TRY(upload(ctx, d_tr, trans.data(), trans.size() * 8));
-    GOAC_TRY(upload(ctx, d_G, G.data(), G.size() * 8));
-    GOAC_TRY(upload(ctx, d_A, &c.A[0][0], 9 * 8));
+    // the tables in the workspace's layout, one copy
+    std::vector<char> img(b_frac + b_pos + b_tr + b_G + b_A, 0);
+    std::memcpy(img.data(), frac.data(), frac.size() * 8);
+    std::memcpy(img.data() + b_frac, cpos.data(), cpos.size() * 8);
+    if (!trans.empty()) std::memcpy(img.data() + b_frac + b_pos, trans.data(), trans.size() * 8);
+    if (!G.empty()) std::memcpy(img.data() + b_frac + b_pos + b_tr, G.data(), G.size() * 8);
+    std::memcpy(img.data() + b_frac + b_pos + b_tr + b_G, &c.A[0][0], 9 * 8);
+    GOAC_TRY(upload(ctx, d_frac, img.data(), img.size()));
     const double cst = -ke * kPi / (c.vol * alpha * alpha);
     const double self = ke * 2.0 * alpha / std::sqrt(kPi);
     {

@@ -6,74 +6,17 @@
 namespace goac {
 
 // ------------------------------------------------------------------ random starts
-// One wavefront per (chain, sublattice): the canonical species sequence of the
+// One workgroup per (chain, sublattice): the canonical species sequence of the
 // sublattice is shuffled by Fisher-Yates. The draws m_k = (r_k (k+1)) >> 32 are
 // independent (counter-based), so the lanes compute them in parallel; the swaps,
-// which are order-dependent, run in sequence: for sublattices of up to
-// kInitRegMax positions on the sequence held in registers (position x in byte
-// (x >> 6) & 3 of dword x >> 8 of lane x & 63, moved between lanes with
-// readlane), else on one lane over LDS.
-constexpr int kInitRegMax = 1024;
-
-template <int NR>
-__device__ void shuffle_regs(uint8_t* arr, const uint16_t* mk, int Ps, int lane) {
-    uint32_t R[NR], D[2 * NR];
-#pragma unroll
-    for (int d = 0; d < NR; ++d) {
-        uint32_t r = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = (4 * d + k) * 64 + lane;
-            if (x < Ps) r |= (uint32_t)arr[x] << (8 * k);
-        }
-        R[d] = r;
-    }
-    // draws: chunk c (positions 64 c + lane) in half c & 1 of D[c >> 1]
-#pragma unroll
-    for (int c2 = 0; c2 < 2 * NR; ++c2) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int x = (2 * c2 + h) * 64 + lane;
-            if (x >= 1 && x < Ps) w |= (uint32_t)mk[x] << (16 * h);
-        }
-        D[c2] = w;
-    }
-    auto byte_at = [&](int x) -> uint32_t {
-        const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)R[x >> 8], x & 63);
-        return (v >> (8 * ((x >> 6) & 3))) & 0xffu;
-    };
-    auto put = [&](int x, uint32_t b) {
-        const uint32_t sh = 8u * (uint32_t)((x >> 6) & 3);
-        const uint32_t old = R[x >> 8];
-        const uint32_t nv = (old & ~(0xffu << sh)) | (b << sh);
-        R[x >> 8] = lane == (x & 63) ? nv : old;
-    };
-    for (int k = Ps - 1; k >= 1; --k) {
-        const uint32_t dw = (uint32_t)__builtin_amdgcn_readlane((int)D[k >> 7], k & 63);
-        const int m = (int)((dw >> (16 * ((k >> 6) & 1))) & 0xffffu);
-        const uint32_t vk = byte_at(k), vm = byte_at(m);
-        put(k, vm);
-        put(m, vk);
-    }
-#pragma unroll
-    for (int d = 0; d < NR; ++d)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = (4 * d + k) * 64 + lane;
-            if (x < Ps) arr[x] = (uint8_t)((R[d] >> (8 * k)) & 0xffu);
-        }
-}
-
-__global__ __launch_bounds__(64) void k_init(int64_t n, int32_t S, int32_t E, const int32_t* __restrict__ tab,
-                                             const int32_t* __restrict__ spos, const int32_t* __restrict__ mob,
-                                             const int32_t* __restrict__ fixed_idx, int32_t n_fixed,
-                                             const uint8_t* __restrict__ ref_occ, uint64_t seed, uint32_t chain_base,
-                                             uint32_t instance, uint8_t* __restrict__ occ) {
+// which are order-dependent, run on one lane.
+__global__ void k_init(int64_t n, int32_t S, int32_t E, const int32_t* __restrict__ tab,
+                       const int32_t* __restrict__ spos, const int32_t* __restrict__ mob,
+                       const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ,
+                       uint64_t seed, uint32_t chain_base, uint32_t instance, uint8_t* __restrict__ occ) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int64_t c = blockIdx.x / S;
     const int s = (int)(blockIdx.x - c * S);
-    const int lane = threadIdx.x;
     const int32_t* subsize = tab + 2;
     const int32_t* suboff = subsize + S;
     const int32_t* cnt = suboff + S;
@@ -82,7 +25,7 @@ __global__ __launch_bounds__(64) void k_init(int64_t n, int32_t S, int32_t E, co
     uint8_t* arr = lds;
     uint16_t* mk = reinterpret_cast<uint16_t*>(lds + round_up(Ps, 16));
     const uint32_t chain = chain_base + (uint32_t)c;
-    for (int x = lane; x < Ps; x += 64) {
+    for (int x = threadIdx.x; x < Ps; x += blockDim.x) {
         int e = 0;
         while (!(x < offs[s * E + e] + cnt[s * E + e])) ++e;
         arr[x] = (uint8_t)e;
@@ -92,25 +35,18 @@ __global__ __launch_bounds__(64) void k_init(int64_t n, int32_t S, int32_t E, co
         }
     }
     __syncthreads();
-    if (Ps <= 256) {
-        shuffle_regs<1>(arr, mk, Ps, lane);
-    } else if (Ps <= 512) {
-        shuffle_regs<2>(arr, mk, Ps, lane);
-    } else if (Ps <= kInitRegMax) {
-        shuffle_regs<4>(arr, mk, Ps, lane);
-    } else if (lane == 0) {
+    if (threadIdx.x == 0)
         for (int k = Ps - 1; k >= 1; --k) {
             const int m = mk[k];
             const uint8_t t = arr[k];
             arr[k] = arr[m];
             arr[m] = t;
         }
-    }
     __syncthreads();
     uint8_t* row = occ + c * n;
-    for (int x = lane; x < Ps; x += 64) row[mob[spos[suboff[s] + x]]] = arr[x];
+    for (int x = threadIdx.x; x < Ps; x += blockDim.x) row[mob[spos[suboff[s] + x]]] = arr[x];
     if (s == 0)
-        for (int f = lane; f < n_fixed; f += 64) row[fixed_idx[f]] = ref_occ[fixed_idx[f]];
+        for (int f = threadIdx.x; f < n_fixed; f += blockDim.x) row[fixed_idx[f]] = ref_occ[fixed_idx[f]];
 }
 
 // ------------------------------------------------------------------ GA: selection tables

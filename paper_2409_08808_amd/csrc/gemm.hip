@@ -24,8 +24,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // columns beyond N are skipped; K is zero-padded. With split-K (gridDim.z > 1)
 // each z-slice writes its partial product to `part`, reduced in slice order by
 // k_dgemm_reduce (deterministic). With sym (A = B, M = N: C += alpha A A^T), only
-// the tiles on and above the diagonal are computed; each mirrors its result into
-// the transposed tile (each element keeping its own beta C term).
+// the tiles on and above the diagonal are computed; each mirrors its result (or
+// its partial) into the transposed tile (each element keeping its own beta C term).
 constexpr int DG_BM = 64, DG_BN = 64, DG_BK = 16;
 static_assert(DG_BM == DG_BN, "the symmetric product mirrors square tiles");
 
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t 
                 if (r < M && cix < N) {
                     if (part) {
                         part[((int64_t)blockIdx.z * M + r) * N + cix] = acc[a][b][v];
+                        if (sym && blockIdx.y < blockIdx.x) part[((int64_t)blockIdx.z * M + cix) * N + r] = acc[a][b][v];
                     } else {
                         double* c = C + r * ldc + cix;
                         const double val = alpha * acc[a][b][v];
@@ -115,14 +116,12 @@ __global__ __launch_bounds__(256) void k_dgemm_nt(int64_t M, int64_t N, int64_t 
 
 // C = alpha sum_z part[z] + beta C, slices summed in order
 __global__ void k_dgemm_reduce(int64_t M, int64_t N, int32_t splits, const double* __restrict__ part,
-                               double* __restrict__ C, int64_t ldc, double alpha, double beta, int32_t sym) {
+                               double* __restrict__ C, int64_t ldc, double alpha, double beta) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t r = idx / N, c = idx - r * N;
-    // below the diagonal tiles, a symmetric product's partials sit transposed
-    const int64_t src = (sym && r / DG_BM > c / DG_BN) ? c * N + r : idx;
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + src];
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
     double* o = C + r * ldc + c;
     const double val = alpha * s;
     *o = (beta == 0.0) ? val : val + beta * *o;
@@ -139,7 +138,7 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
     // split K when the tile grid leaves most compute units idle and K is long
     int splits = 1;
     const int64_t want = 2 * (int64_t)ctx->num_cus;
-    while (!M_dev && tiles * splits < want && K / (splits * 2) >= 512 && splits < 32) splits *= 2;
+    while (!M_dev && tiles * splits < want && K / (splits * 2) >= 256 && splits < 32) splits *= 2;
     const int64_t kps = round_up((K + splits - 1) / splits, DG_BK);
     double* part = nullptr;
     if (splits > 1) {
@@ -154,7 +153,7 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
     GOAC_CHECK_LAUNCH(ctx);
     if (splits > 1) {
         hipLaunchKernelGGL(k_dgemm_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, ctx->stream, M, N,
-                           splits, part, C, ldc, alpha, beta, sym ? 1 : 0);
+                           splits, part, C, ldc, alpha, beta);
         GOAC_CHECK_LAUNCH(ctx);
     }
     return GOAC_OK;
