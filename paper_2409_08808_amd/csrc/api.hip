@@ -811,7 +811,7 @@ extern "C" goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
     if (lds > 64 * 1024)
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_init, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_init, dim3((unsigned)(C * d.S)), dim3(256), lds, ctx->stream, d.n, d.S, d.E, d.tab, pb->spos,
+    hipLaunchKernelGGL(k_init, dim3((unsigned)(C * d.S)), dim3(128), lds, ctx->stream, d.n, d.S, d.E, d.tab, pb->spos,
                        d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, seed, chain_base, instance, occ);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
