@@ -261,8 +261,10 @@ goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_
  * E_k the energy of the chain at temperature k and u = ((r0:r1 >> 12) + 1/2)
  * 2^-52 from Philox at counter (k, x_lo, x_hi, group << 8 | 6), key seed.
  * Configurations stay with their chains; the chains' temperature rows move.
+ *   R        : replicas per group, 2 <= R <= 2^19, dividing C
  *   slot_dev : (C / R) x R int32, the chain (index within its group) at each
- *              temperature, in/out
+ *              temperature, in/out; a group whose row is not a permutation of
+ *              0 .. R-1 is left unchanged
  *   acc_dev  : (C / R) x R uint8: 1 where the pair (k, k+1) attempted at this step
  *              was accepted, 0 elsewhere (may be NULL)
  * Sweeps after an exchange run chain c at row = its temperature index. */
@@ -350,8 +352,10 @@ typedef struct {
  *              rows are set from it at the start
  *   pop_dev  : P x n population (in/out); E_dev : P FP64, the energies of the
  *              returned population (out)
- * Synchronises (composition check of the reload). The chain set owns the scratch
- * memory of the round (grown on demand, freed with the chains). */
+ * Synchronises twice: once after the GA phase (a roulette failure in any of its
+ * generations is reported then, GOAC_EINVAL) and once for the composition check
+ * of the reload. The chain set owns the scratch memory of the round (grown on
+ * demand, freed with the chains). */
 goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int64_t P, uint8_t* pop_dev, double* E_dev,
                               const goac_hybrid_params* params);
 

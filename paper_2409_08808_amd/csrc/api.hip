@@ -446,33 +446,75 @@ __global__ void k_export(int64_t n, int32_t M, const int32_t* __restrict__ mob, 
     }
 }
 
-// replica exchange: one thread per group of R consecutive chains
-// x_dev, when given, holds the exchange step index (a captured round reads it)
-__global__ void k_remc(int64_t n_groups, int32_t R, const double* __restrict__ kT, uint64_t x,
-                       const uint64_t* __restrict__ x_dev, uint64_t seed, ChainScalars* __restrict__ sc,
-                       int32_t* __restrict__ slot, uint8_t* __restrict__ acc) {
-    const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gidx >= n_groups) return;
-    if (x_dev) x = *x_dev;
-    int32_t* sl = slot + gidx * R;
-    if (acc)
-        for (int k = 0; k < R; ++k) acc[gidx * R + k] = 0;
-    for (int k = 0; k < R; ++k)
-        if ((uint32_t)sl[k] >= (uint32_t)R) return;    // not a permutation: left unchanged
-    for (int k = (int)(x & 1u); k + 1 < R; k += 2) {
-        const u32x4 r = philox((uint32_t)k, (uint32_t)x, (uint32_t)(x >> 32), ((uint32_t)gidx << 8) | TAG_REMC, seed);
-        const double u = unit_open(r.x, r.y);
-        const double Ea = sc[gidx * R + sl[k]].E, Eb = sc[gidx * R + sl[k + 1]].E;
-        const double arg = (Ea - Eb) * (1.0 / kT[k] - 1.0 / kT[k + 1]);
-        const bool ok = (arg >= 0.0) || (u < exp(arg));
-        if (acc) acc[gidx * R + k] = ok ? 1 : 0;
-        if (ok) {
-            const int32_t t = sl[k];
-            sl[k] = sl[k + 1];
-            sl[k + 1] = t;
+// replica exchange: one workgroup per group of R consecutive chains. The slots
+// are checked to be a permutation of 0..R-1 (an LDS bit per value); the pairs of
+// the step are disjoint, so each is decided by its own thread and the outcome is
+// that of deciding them in order. x_dev, when given, holds the step index (a
+// captured round reads it); the last workgroup to finish then advances it and
+// clears the sweep's work counter for the next round.
+__global__ void k_remc(int32_t R, const double* __restrict__ kT, uint64_t x, uint64_t* x_dev, uint64_t seed,
+                       ChainScalars* __restrict__ sc, int32_t* __restrict__ slot, uint8_t* __restrict__ acc,
+                       uint32_t* ticket, int32_t* queue) {
+    extern __shared__ uint32_t seen[];
+    __shared__ int s_bad;
+    __shared__ uint64_t s_x;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int64_t g = blockIdx.x;
+    int32_t* sl = slot + g * R;
+    ChainScalars* gs = sc + g * R;
+    for (int w = tid; w < (R + 31) / 32; w += bs) seen[w] = 0;
+    if (tid == 0) {
+        s_bad = 0;
+        s_x = x_dev ? *x_dev : x;   // read once, before this workgroup takes its ticket
+    }
+    __syncthreads();
+    x = s_x;
+    for (int k = tid; k < R; k += bs) {
+        const int32_t v = sl[k];
+        if (acc) acc[g * R + k] = 0;
+        if ((uint32_t)v >= (uint32_t)R) {
+            s_bad = 1;
+        } else {
+            const uint32_t bit = 1u << (v & 31);
+            if (atomicOr(&seen[v >> 5], bit) & bit) s_bad = 1;
         }
     }
-    for (int k = 0; k < R; ++k) sc[gidx * R + sl[k]].row = k;
+    __syncthreads();
+    if (!s_bad) {   // otherwise the group is left unchanged
+        const int par = (int)(x & 1u);
+        for (int k = par + 2 * tid; k + 1 < R; k += 2 * bs) {
+            const int32_t a = sl[k], b = sl[k + 1];
+            const u32x4 r = philox((uint32_t)k, (uint32_t)x, (uint32_t)(x >> 32), ((uint32_t)g << 8) | TAG_REMC, seed);
+            const double u = unit_open(r.x, r.y);
+            const double arg = (gs[a].E - gs[b].E) * (1.0 / kT[k] - 1.0 / kT[k + 1]);
+            const bool ok = (arg >= 0.0) || (u < exp(arg));
+            if (acc) acc[g * R + k] = ok ? 1 : 0;
+            if (ok) {
+                sl[k] = b;
+                sl[k + 1] = a;
+            }
+            gs[ok ? b : a].row = k;
+            gs[ok ? a : b].row = k + 1;
+        }
+        // the positions outside every pair keep their chains
+        if (tid == 0) {
+            if (par) gs[sl[0]].row = 0;
+            if ((R - par) & 1) gs[sl[R - 1]].row = R - 1;
+        }
+    }
+    if (ticket) {
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            if (atomicAdd(ticket, 1u) == gridDim.x - 1) {
+                __threadfence();
+                *ticket = 0;
+                *queue = 0;
+                *x_dev = x + 1;
+                __threadfence();
+            }
+        }
+    }
 }
 
 __global__ void k_set_rows(int64_t C, const int32_t* __restrict__ rows, ChainScalars* __restrict__ sc) {
@@ -480,8 +522,12 @@ __global__ void k_set_rows(int64_t C, const int32_t* __restrict__ rows, ChainSca
     if (c < C) sc[c].row = rows[c];
 }
 
-__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
-__global__ void k_inc_u64(uint64_t* p) { *p += 1; }
+// step index, ticket and work counter of a captured replica-exchange round
+__global__ void k_remc_init(uint64_t* x_dev, uint64_t x0, uint32_t* ticket, int32_t* queue) {
+    *x_dev = x0;
+    *ticket = 0;
+    *queue = 0;
+}
 
 __global__ void k_zero_i32(int32_t* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -554,6 +600,7 @@ extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     for (int h = 0; h < 2; ++h)
         if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
@@ -849,9 +896,12 @@ extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t
 }
 
 // ------------------------------------------------------------------ GA
-extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
-                                          const goac_ga_params* prm, uint8_t* pop_out) {
-    if (!pb) return GOAC_EINVAL;
+namespace goac {
+
+// one generation queued on the context's stream; a roulette-weight failure is
+// or-ed into *err_out (cleared first when zero_err), which the caller reads
+goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
+                                  const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out) {
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || !pop_in || !E_in || !prm || !pop_out || pop_in == pop_out || !(prm->p_mut >= 0.0))
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
@@ -867,16 +917,31 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
     int32_t* elite = (int32_t*)((char*)ws + b_cum);
     int32_t* cnt = (int32_t*)((char*)ws + b_cum + b_el);
     int32_t* err = (int32_t*)((char*)ws + b_cum + b_el + b_cnt);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, err, 1);
+    if (zero_err) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, err, 1);
     hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, cum, err);
     GOAC_CHECK_LAUNCH(ctx);
     GOAC_TRY(rank_select(ctx, P, E_in, ne, cnt, nullptr, elite, nullptr));
     GOAC_TRY(ga_children(pb, P, pop_in, cum, elite, ne, prm, pop_out));
+    *err_out = err;
+    return GOAC_OK;
+}
+
+goac_status ga_check_err(goac_ctx* ctx, const int32_t* err) {
     int32_t herr = 0;
     GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, ctx->stream));
     GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (herr) return fail(ctx, GOAC_EINVAL, "ga_generation: energy spread too large for the roulette weights");
     return GOAC_OK;
+}
+
+}  // namespace goac
+
+extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
+                                          const goac_ga_params* prm, uint8_t* pop_out) {
+    if (!pb) return GOAC_EINVAL;
+    int32_t* err = nullptr;
+    GOAC_TRY(ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err));
+    return ga_check_err(pb->ctx, err);
 }
 
 // ------------------------------------------------------------------ chains
@@ -885,7 +950,6 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
 static goac_status chains_build(goac_chains* ch, const uint8_t* occ) {
     goac_ctx* ctx = ch->ctx;
     const int n_inst = (int)ch->pbs.size();
-    hipStream_t sm = ctx->stream;
     const bool mixed = ch->prec == GOAC_MIXED;
     const int64_t C = ch->C;
     // per-chain offsets
@@ -1134,10 +1198,13 @@ static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg
     // one-wave chains gather V_mm entries through 32-bit byte offsets
     if ((uint64_t)ch->max_Mp * (uint64_t)ch->max_Mp * 8u >= ((uint64_t)1 << 32)) wg = 256;
     const size_t phi_bytes = (size_t)round_up(ch->max_Mp * (mixed ? 4 : 8), 16);
-    // occupation, site class (only with several classes), perm and where per position
+    // occupation, site class (only with several classes), perm and where per
+    // position; one-wave chains add the FP64 diagonal
     const bool msub_lds = ch->max_S > 1;
-    const size_t lds = phi_bytes + (size_t)ch->max_Mp * (1 + (msub_lds ? 1 : 0) + 2 + 2) +
-                       round_up(ch->max_tab * 4, 16) + kMaxSpecies * 8;
+    const size_t lds_base = phi_bytes + (size_t)ch->max_Mp * (1 + (msub_lds ? 1 : 0) + 2 + 2) +
+                            round_up(ch->max_tab * 4, 16) + kMaxSpecies * 8;
+    if (wg == 64 && lds_base + (size_t)ch->max_Mp * 8 > 160 * 1024) wg = 256;   // no room for it
+    const size_t lds = lds_base + (wg == 64 ? (size_t)ch->max_Mp * 8 : 0);
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "mc_sweep: the chain state does not fit in LDS");
     const int cap = std::max<int>(1, std::min<int>(wg == 64 ? 16 : 4, (int)((160 * 1024) / lds)));
     const int per_cu = per_cu_req > 0 ? std::min(per_cu_req, cap) : cap;
@@ -1196,14 +1263,15 @@ static goac_status sweep_upload_kT(goac_chains* ch, const double* kT_host, size_
 // the launches of a sweep: kernels only (no host copies), so a stream capture may
 // record them. The persistent grid pulls chains from a counter reset before each
 // launch.
+// zero_queue false: the caller has cleared the work counter (one launch only)
 static goac_status sweep_enqueue(goac_chains* ch, SweepPlan P, bool trace, uint64_t n_trials,
-                                 int32_t reanchor_every) {
+                                 int32_t reanchor_every, bool zero_queue = true) {
     goac_ctx* ctx = ch->ctx;
     const bool mixed = ch->prec == GOAC_MIXED;
     P.a.kT = ch->kT;
     if (P.a.inline_anchor) {
         P.a.n_trials = n_trials;
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+        if (zero_queue) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
         return mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid);
     }
     const uint64_t chunk = (uint64_t)reanchor_every * 8;
@@ -1348,12 +1416,23 @@ extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t
     return GOAC_OK;
 }
 
+// replicas per group: the permutation check keeps one LDS bit per slot value
+constexpr int32_t kRemcMaxR = 1 << 19;
+
+static void remc_launch(hipStream_t s, int64_t ng, int32_t R, const double* kT, uint64_t x, uint64_t* x_dev,
+                        uint64_t seed, ChainScalars* sc, int32_t* slot, uint8_t* acc, uint32_t* ticket,
+                        int32_t* queue) {
+    const size_t lds = (size_t)((R + 31) / 32) * 4;
+    hipLaunchKernelGGL(k_remc, dim3((unsigned)ng), dim3(R <= 128 ? 64 : 256), lds, s, R, kT, x, x_dev, seed, sc,
+                       slot, acc, ticket, queue);
+}
+
 extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host, uint64_t x,
                                           uint64_t seed, int32_t* slot, uint8_t* acc) {
     if (!ch) return GOAC_EINVAL;
     goac_ctx* ctx = ch->ctx;
-    if (R < 2 || !kT_host || !slot || ch->C % R != 0)
-        return fail(ctx, GOAC_EINVAL, "remc_exchange: R must be >= 2 and divide the chain count");
+    if (R < 2 || R > kRemcMaxR || !kT_host || !slot || ch->C % R != 0)
+        return fail(ctx, GOAC_EINVAL, "remc_exchange: R must be in [2, 2^19] and divide the chain count");
     for (int k = 0; k < R; ++k)
         if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_exchange: kT must be positive");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
@@ -1375,8 +1454,7 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
     }
     const double* d = ch->ladder;
     const int64_t ng = ch->C / R;
-    hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, ctx->stream, ng, R, d, x,
-                       (const uint64_t*)nullptr, seed, ch->sc, slot, acc);
+    remc_launch(ctx->stream, ng, R, d, x, nullptr, seed, ch->sc, slot, acc, nullptr, nullptr);
     GOAC_CHECK_LAUNCH(ctx);
     ch->max_row = std::max(ch->max_row, R - 1);
     return GOAC_OK;
@@ -1392,7 +1470,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
                                      int32_t reanchor_every, int32_t* slot) {
     if (!ch) return GOAC_EINVAL;
     goac_ctx* ctx = ch->ctx;
-    if (R < 2 || !kT_host || !slot || ch->C % R != 0 || trials == 0 || (flags & ~GOAC_MC_TRACE_HASH))
+    if (R < 2 || R > kRemcMaxR || !kT_host || !slot || ch->C % R != 0 || trials == 0 || (flags & ~GOAC_MC_TRACE_HASH))
         return fail(ctx, GOAC_EINVAL, "remc_run: bad arguments");
     for (int k = 0; k < R; ++k)
         if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_run: kT must be positive");
@@ -1421,8 +1499,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     if (!P.a.inline_anchor) {
         for (uint64_t r = 0; r < rounds; ++r) {
             GOAC_TRY(sweep_enqueue(ch, P, trace, trials, prm.reanchor_every));
-            hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, sm, ng, R, ch->kT, x0 + r,
-                               (const uint64_t*)nullptr, seed, ch->sc, slot, (uint8_t*)nullptr);
+            remc_launch(sm, ng, R, ch->kT, x0 + r, nullptr, seed, ch->sc, slot, nullptr, nullptr, nullptr);
             GOAC_CHECK_LAUNCH(ctx);
         }
         return GOAC_OK;
@@ -1430,12 +1507,14 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     void* xs = nullptr;
     GOAC_TRY(workspace(ctx, 2, 256, &xs));
     uint64_t* xdev = (uint64_t*)xs;
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, sm, xdev, x0);
+    uint32_t* ticket = (uint32_t*)(xdev + 1);
+    // the first round's work counter is cleared here, later ones by the exchange
+    hipLaunchKernelGGL(k_remc_init, dim3(1), dim3(1), 0, sm, xdev, x0, ticket, ch->queue);
     GOAC_CHECK_LAUNCH(ctx);
     // capture on a private stream (the context's may be the null stream, which
     // cannot be captured); the graph then runs on the context's stream
-    hipStream_t cap = nullptr;
-    GOAC_HIP(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (!ctx->cap) GOAC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    hipStream_t cap = ctx->cap;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ctx->stream = cap;
@@ -1443,12 +1522,9 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     goac_status st = GOAC_OK;
     hipError_t ec = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (ec == hipSuccess) {
-        st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every);
-        if (st == GOAC_OK) {
-            hipLaunchKernelGGL(k_remc, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cap, ng, R, ch->kT,
-                               (uint64_t)0, (const uint64_t*)xdev, seed, ch->sc, slot, (uint8_t*)nullptr);
-            hipLaunchKernelGGL(k_inc_u64, dim3(1), dim3(1), 0, cap, xdev);
-        }
+        st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every, false);
+        if (st == GOAC_OK)
+            remc_launch(cap, ng, R, ch->kT, 0, xdev, seed, ch->sc, slot, nullptr, ticket, ch->queue);
         ec = hipStreamEndCapture(cap, &graph);
     }
     ctx->stream = sm;
@@ -1458,7 +1534,6 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     if (st == GOAC_OK && ec == hipSuccess) ec = hipStreamSynchronize(sm);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cap);
     if (st != GOAC_OK) return st;
     if (ec != hipSuccess) return fail(ctx, GOAC_EHIP, std::string("remc_run: graph: ") + hipGetErrorString(ec));
     return GOAC_OK;

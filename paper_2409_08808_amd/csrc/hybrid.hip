@@ -131,18 +131,21 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)P), dim3(256), 0, sm, P, n, idx, cand, pop_dev);
     GOAC_CHECK_LAUNCH(ctx);
     // 3. GA phase (double-buffered; the result ends in pop_dev)
+    // (a failed roulette is reported once, after the last generation)
     uint8_t* cur = pop_dev;
     uint8_t* other = pop2;
+    int32_t* ga_err = nullptr;
     for (int32_t k = 0; k < prm->generations; ++k) {
         goac_ga_params gp{};
         gp.seed = prm->seed;
         gp.generation = (uint32_t)(prm->round * (uint64_t)prm->generations + (uint64_t)k);
         gp.n_elite = prm->n_elite;
         gp.p_mut = prm->p_mut;
-        GOAC_TRY(goac_ga_generation(pb, P, cur, E_dev, &gp, other));
+        GOAC_TRY(ga_generation_enqueue(pb, P, cur, E_dev, &gp, other, k == 0, &ga_err));
         GOAC_TRY(goac_energies(pb, P, other, (goac_precision)prm->precision, E_dev));
         std::swap(cur, other);
     }
+    if (ga_err) GOAC_TRY(ga_check_err(ctx, ga_err));
     if (cur != pop_dev) GOAC_HIP(ctx, hipMemcpyAsync(pop_dev, cur, (size_t)(P * n), hipMemcpyDeviceToDevice, sm));
     // 4. GA -> REMC: the best individuals to the groups' coldest replicas
     const int32_t n_inj = (int32_t)std::max<int64_t>(1, std::min<int64_t>(prm->inject, P));

@@ -2,7 +2,8 @@
 //
 // One workgroup runs one chain at a time; a persistent grid pulls chains from a
 // work counter in longest-first order. A chain's field phi, its occupation and
-// its per-sublattice position lists live in LDS for the whole launch.
+// its per-sublattice position lists live in LDS for the whole launch (one-wave
+// chains also keep the diagonal V_kk there, two of the three per-trial gathers).
 //
 // Trials are evaluated speculatively: the WG lanes score the next WG trial
 // indices t, t+1, ... against the current state at once (Philox draw, partner
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     uint16_t* where = perm + a.Mp_max;
     int32_t* tab = reinterpret_cast<int32_t*>(where + a.Mp_max);
     double* chg = reinterpret_cast<double*>(tab + a.tab_max);
+    double* dgl = chg + kMaxSpecies;   // one-wave chains: the diagonal V_kk of the instance
 
     if (tid == 0) s_flag = 0;
     for (int round = 0;; ++round) {
@@ -238,6 +240,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         }
         for (int k = tid; k < ntab; k += WG) tab[k] = gptr(I.tab)[k];
         for (int k = tid; k < E; k += WG) chg[k] = gptr(I.charge)[k];
+        if constexpr (WG == 64) for (int k = tid; k < M; k += WG) dgl[k] = diag[k];
         __syncthreads();
         for (int k = tid; k < M; k += WG) where[perm[k]] = (uint16_t)k;
         if (MIXED && tid < S) s_phibar[tid] = gptr(I.phibar)[tid];
@@ -322,7 +325,9 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
             auto score = [&]() {
                 i = (int)mulshift(r.x, (uint32_t)M);
                 // the loads that need only i go out first
-                const double Vii = gather<WG == 64>(diag, (uint32_t)i);
+                double Vii;
+                if constexpr (WG == 64) Vii = dgl[i];
+                else Vii = gather<false>(diag, (uint32_t)i);
                 const double phi_i = (double)phi[i];
                 const int s = S == 1 ? 0 : msub[i];
                 const int sa = occ[i];
@@ -336,7 +341,9 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                 const int idx = k < offs[se] ? k : k + na;
                 const int jp = perm[suboff[s] + idx];
                 j = csz > 0 ? jp : i;
-                const double Vjj = gather<WG == 64>(diag, (uint32_t)j);
+                double Vjj;
+                if constexpr (WG == 64) Vjj = dgl[j];
+                else Vjj = gather<false>(diag, (uint32_t)j);
                 const double Vij = gather<WG == 64>(V64, __umul24((unsigned)i, (unsigned)Mp) + (unsigned)j);
                 const double phi_j = (double)phi[j];
                 const int sb = occ[j];

@@ -272,6 +272,51 @@ def test_remc_exchange_bitexact(ctx, cfg1):
         assert np.array_equal(ref_slot[g][rows[g]], np.arange(R))
 
 
+@pytest.mark.parametrize("R", [2, 5, 130, 600])
+def test_remc_exchange_ladders(ctx, cfg1, R):
+    """Odd and long ladders (several pairs per thread at R = 600) against the
+    oracle's exchange; a group whose slots repeat a chain is left unchanged while
+    the other group goes on."""
+    cell, V = cfg1
+    groups = 2
+    ladder = np.geomspace(0.02, 0.6, R)
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    occ0 = pb.init_occupations(R * groups, seed=R)
+    ch = G.Chains(pb, occ0, G.GOAC_FP64)
+    rng = np.random.default_rng(R)
+    ref_slot = np.stack([rng.permutation(R).astype(np.int32) for _ in range(groups)])
+    rows = np.argsort(ref_slot, axis=1).reshape(-1)
+    ch.set_rows(rows)
+    slot = torch.from_numpy(ref_slot.reshape(-1).copy()).cuda()
+    acc = torch.zeros(R * groups, dtype=torch.uint8, device="cuda")
+    ch.sweep(300, ladder[:, None], seed=2)
+    _, _, stats = ch.export()
+    for x in range(3):
+        ch.remc_exchange(R, ladder, x, 9, slot, acc)
+        got_acc = acc.view(groups, R).cpu().numpy()
+        for g in range(groups):
+            ref_slot[g], ref_acc = O.remc_exchange(ladder, stats["E"][g * R:(g + 1) * R], ref_slot[g], x, 9, group=g)
+            assert np.array_equal(got_acc[g], ref_acc)
+        assert np.array_equal(slot.view(groups, R).cpu().numpy(), ref_slot)
+    _, _, stats = ch.export()
+    rows = stats["row"].reshape(groups, R)
+    for g in range(groups):
+        assert np.array_equal(ref_slot[g][rows[g]], np.arange(R))
+    # a repeated chain in group 1: that group keeps its slots and rows
+    bad = ref_slot.copy()
+    bad[1, 0] = bad[1, 1]
+    slot = torch.from_numpy(bad.reshape(-1).copy()).cuda()
+    ch.remc_exchange(R, ladder, 3, 9, slot, acc)
+    ref0, _ = O.remc_exchange(ladder, stats["E"][:R], ref_slot[0], 3, 9, group=0)
+    got = slot.view(groups, R).cpu().numpy()
+    assert np.array_equal(got[0], ref0) and np.array_equal(got[1], bad[1])
+    assert not acc.view(groups, R)[1].any()
+    _, _, st2 = ch.export()
+    assert np.array_equal(st2["row"].reshape(groups, R)[1], rows[1])
+    ch.close()
+    pb.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_autotune_leaves_chains_unchanged(ctx, cfg2, prec):
     """The tuner's probe sweeps leave the chains as they were, and sweeps with the
@@ -291,14 +336,15 @@ def test_autotune_leaves_chains_unchanged(ctx, cfg2, prec):
     _compare(cell, stats, occ.cpu().numpy(), best.cpu().numpy(), st, prec, V)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec):
+@pytest.mark.parametrize("prec,groups", [(0, 16), (1, 16), (1, 1100)])
+def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups):
     """Rounds replayed from one captured graph equal the same rounds launched one
     by one (sweep + exchange), bit for bit; checked after several replays, after a
     second call that captures again, and with eager work and synchronisation
-    between the calls."""
+    between the calls. 4400 chains are more than the resident workgroups, so the
+    sweep's work counter, cleared by each round's exchange, is in use."""
     cell, V = cfg2
-    R, groups = 4, 16
+    R = 4
     ladder = np.array([0.05, 0.1, 0.2, 0.4])
     occ0 = O.init_occupations(cell, R * groups, seed=12)
     pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
@@ -325,6 +371,23 @@ def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec):
 
 
 # ------------------------------------------------------------------ GA
+
+def test_ga_generation_reports_roulette_overflow(ctx, cfg1):
+    """An energy spread beyond the integer roulette weights' range is an error
+    (set from the host, the kernels run normally); the next call starts clean."""
+    cell, V = cfg1
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    pop = O.init_occupations(cell, 64, seed=1)
+    E = np.zeros(64)
+    E[3] = -1e9
+    with pytest.raises(G.GoacError, match="roulette"):
+        pb.ga_generation(torch.from_numpy(pop), torch.from_numpy(E), seed=1, generation=0)
+    E = -1000.0 + np.arange(64) * 0.01
+    got = pb.ga_generation(torch.from_numpy(pop), torch.from_numpy(E), seed=1, generation=0).cpu().numpy()
+    ref = O.ga_generation(cell, pop, E, seed=1, g=0)
+    assert np.array_equal(got, ref)
+    pb.close()
+
 
 @pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96),
                                      ("config5", 24), ("many", 40)])
