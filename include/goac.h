@@ -275,10 +275,11 @@ goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host
  * temperature of its slot followed by exchange step x0 + r (r = 0 .. rounds-1);
  * the same as alternating goac_mc_sweep (the ladder as an R x 1 table) and
  * goac_remc_exchange, bit for bit. The chains' rows are set from slot_dev first.
- * One round (the sweep's kernels and the exchange) is captured once as a HIP
- * graph and replayed, the step index read from device memory; cells whose MIXED
- * field re-anchors between sweep chunks (more than 1024 mobile positions) run the
- * same rounds without capture.
+ * Up to 8 rounds (the sweep's kernels and the exchange) are captured once as one
+ * HIP graph and replayed, the step index read from device memory; the rounds % 8
+ * left over launch the same kernels on the stream. Cells whose MIXED field
+ * re-anchors between sweep chunks (more than 1024 mobile positions) run the same
+ * rounds without capture.
  *   flags : 0 or GOAC_MC_TRACE_HASH;  reanchor_every : as in goac_mc_params
  *   slot_dev : groups x R int32 (in/out). Synchronises. */
 goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials, uint64_t rounds,

@@ -1418,6 +1418,8 @@ extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t
 
 // replicas per group: the permutation check keeps one LDS bit per slot value
 constexpr int32_t kRemcMaxR = 1 << 19;
+// rounds per captured graph of goac_remc_run
+constexpr uint64_t kRemcGraphRounds = 8;
 
 static void remc_launch(hipStream_t s, int64_t ng, int32_t R, const double* kT, uint64_t x, uint64_t* x_dev,
                         uint64_t seed, ChainScalars* sc, int32_t* slot, uint8_t* acc, uint32_t* ticket,
@@ -1461,10 +1463,12 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
 }
 
 
-// Many replica-exchange rounds: the sweep of one round and its exchange step are
-// captured once as a graph and replayed, the step index x0 + r read from device
-// memory. Cells whose MIXED field re-anchors between sweep chunks (workspace sized
-// on the host) run the same rounds without capture.
+// Many replica-exchange rounds: up to kRemcGraphRounds rounds (each a sweep and its
+// exchange step) are captured once as a graph and replayed, the step index x0 + r
+// read from device memory and advanced by each exchange; the last rounds that do
+// not fill a graph launch the same kernels on the stream. Cells whose MIXED field
+// re-anchors between sweep chunks (workspace sized on the host) run the same
+// rounds without capture.
 extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials,
                                      uint64_t rounds, uint64_t x0, uint64_t seed, uint32_t flags,
                                      int32_t reanchor_every, int32_t* slot) {
@@ -1520,17 +1524,31 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     ctx->stream = cap;
     ctx->capturing = true;
     goac_status st = GOAC_OK;
+    // a graph holds K rounds: consecutive launches of one graph are separated by a
+    // gap of several microseconds, the kernels inside it are not
+    const uint64_t K = std::min<uint64_t>(rounds, kRemcGraphRounds);
     hipError_t ec = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (ec == hipSuccess) {
-        st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every, false);
-        if (st == GOAC_OK)
-            remc_launch(cap, ng, R, ch->kT, 0, xdev, seed, ch->sc, slot, nullptr, ticket, ch->queue);
+        for (uint64_t q = 0; q < K && st == GOAC_OK; ++q) {
+            st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every, false);
+            if (st == GOAC_OK)
+                remc_launch(cap, ng, R, ch->kT, 0, xdev, seed, ch->sc, slot, nullptr, ticket, ch->queue);
+        }
         ec = hipStreamEndCapture(cap, &graph);
     }
     ctx->stream = sm;
     ctx->capturing = false;
     if (st == GOAC_OK && ec == hipSuccess) ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    for (uint64_t r = 0; st == GOAC_OK && ec == hipSuccess && r < rounds; ++r) ec = hipGraphLaunch(exec, sm);
+    uint64_t r = 0;
+    for (; st == GOAC_OK && ec == hipSuccess && r + K <= rounds; r += K) ec = hipGraphLaunch(exec, sm);
+    // the last rounds % K rounds: the same kernels launched on the stream
+    for (; st == GOAC_OK && ec == hipSuccess && r < rounds; ++r) {
+        st = sweep_enqueue(ch, P, trace, trials, prm.reanchor_every, false);
+        if (st == GOAC_OK) {
+            remc_launch(sm, ng, R, ch->kT, 0, xdev, seed, ch->sc, slot, nullptr, ticket, ch->queue);
+            ec = hipGetLastError();
+        }
+    }
     if (st == GOAC_OK && ec == hipSuccess) ec = hipStreamSynchronize(sm);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);

@@ -132,15 +132,39 @@ __device__ void anchor_chain(const McInst& I, const uint8_t* occ, const uint8_t*
                              const double* phibar, float* phi, double* scr, double& E_out, double& eps_out,
                              float& phib_out) {
     const int M = I.M;
-    const GOAC_GLOBAL double* V64 = gptr(I.V64);
+    const GOAC_GLOBAL double* V64 = gptr(sptr(I.V64));
     const GOAC_GLOBAL double* hv = gptr(I.h);
+    // in-kernel anchors run for cells of at most 1024 positions: 32-bit byte offsets
+    const uint32_t rs = (uint32_t)I.Mp;
     double esum = 0.0, pmax = 0.0, amax = 0.0;
     for (int k0 = 0; k0 < M; k0 += WG) {
         const int k = k0 + threadIdx.x;
         const bool ok = k < M;
         double acc = ok ? hv[k] : 0.0;
         double aab = ok ? fabs(acc) : 0.0;
-        for (int l = 0; l < M; ++l) {
+        // the sum runs over l in order; U rows are loaded ahead of it so that a
+        // one-wave chain keeps U loads in flight (one more U-fold unroll costs the
+        // trial loop scalar registers)
+        constexpr int U = 4;
+        int l = 0;
+        uint32_t o = (uint32_t)k;   // element (l, k)
+        for (; l + U <= M; l += U) {
+            double v[U], q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                q[u] = chg[occ[l + u]];
+                v[u] = ok ? gather<true>(V64, o) : 0.0;
+                o += rs;
+            }
+            if (ok) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    acc += v[u] * q[u];
+                    aab += fabs(v[u] * q[u]);
+                }
+            }
+        }
+        for (; l < M; ++l) {
             const double ql = chg[occ[l]];
             if (ok) {
                 const double v = V64[(int64_t)l * I.Mp + k];

@@ -354,7 +354,7 @@ def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups):
     sb = sa.clone()
     b.set_rows(np.tile(np.arange(R), groups))
     x = 0
-    for rounds in (3, 1, 4):
+    for rounds in (3, 1, 11):
         a.remc_run(R, ladder, 700, rounds, x, 5, sa, trace=True)
         for r in range(rounds):
             b.sweep(700, ladder[:, None], 700, seed=5, trace=True)
