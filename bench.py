@@ -233,9 +233,43 @@ def ga_energies(ctx, G, S, torch, stream, generations):
             # and lo: 2 x 2 x P x M (M + 1) / 2 flops per call
             flops = 2 * 2.0 * 1024 * 2048 * 2049 / 2
             out["ga_mixed_mfma_frac"] = flops / (t_en / gens) / BF16_PEAK
+            out["ga_run_mixed_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, prec, 1024, gens)
     out["energies_per_s"] = out["ga_mixed_energies_per_s"]
     pb.close()
+    # the same generation loop on the 4x4x4 cell (M = 256), where a generation is short
+    # enough for the per-call work to show: generation by generation from Python
+    # against goac_ga_run (graph replays)
+    cell = S.config2()
+    V = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    del V
+    gens = 100
+    pop = pb.init_occupations(1024, seed=0)
+    E = pb.energies(pop, G.GOAC_MIXED)
+    pb.ga_generation(pop, E, seed=0, generation=0)             # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(gens):
+        pop = pb.ga_generation(pop, E, seed=0, generation=g, n_elite=8, p_mut=0.2)
+        pb.energies(pop, G.GOAC_MIXED, out=E)
+    torch.cuda.synchronize()
+    out["ga_cfg2_loop_generation_ms"] = 1e3 * (time.perf_counter() - t0) / gens
+    out["ga_cfg2_run_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, G.GOAC_MIXED, 1024, gens)
+    pb.close()
     return out
+
+
+def ga_run_time(G, pb, torch, prec, P, gens):
+    """Seconds per generation of goac_ga_run over `gens` generations (bf16 or FP64
+    energies after each), after an untimed warm-up call."""
+    pop = pb.init_occupations(P, seed=1)
+    E = pb.energies(pop, prec)
+    pb.ga_run(pop, E, seed=1, generation=0, generations=20, precision=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.ga_run(pop, E, seed=1, generation=20, generations=gens, precision=prec)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / gens
 
 
 def large_cell(ctx, G, S, torch, stream):

@@ -58,6 +58,9 @@ typedef struct goac_chains goac_chains;
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or
  * NULL for the null stream). The stream is borrowed, not owned. */
 goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** out);
+/* Release the context. Its memory is freed (after waiting for its stream) once
+ * every problem and chain set made on it has been destroyed too, so these may be
+ * destroyed before or after the context; no other call may use it afterwards. */
 void goac_ctx_destroy(goac_ctx* ctx);
 /* Message of the last failed call on ctx; valid until the next call on ctx. */
 const char* goac_last_error(const goac_ctx* ctx);
@@ -309,6 +312,22 @@ typedef struct {
 goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
+
+/* `generations` GA generations in a row (SI, "Genetic Algorithm": the population
+ * evolves generation after generation), bit for bit the same as alternating
+ * goac_ga_generation (generation index params->generation + k, k = 0 ..
+ * generations-1) and goac_energies of the children in `precision`. After the first
+ * generation, eight generations at a time are captured once as one HIP graph and
+ * replayed (when at least sixteen remain), the generation index read from a
+ * device counter; the rest run on the stream.
+ *   pop_dev : P x n (in/out): the population, then the last generation's children
+ *   E_dev   : P FP64 (in/out): energies of pop_dev, then of the returned population
+ *   precision : GOAC_FP64 or GOAC_MIXED
+ * Errors: EINVAL as goac_ga_generation (the roulette range is checked once, after
+ * the last generation; pop_dev and E_dev are then unspecified). Synchronises;
+ * takes a second population buffer from the context's cache for the call. */
+goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop_dev, double* E_dev,
+                        const goac_ga_params* params, int32_t generations, int32_t precision);
 
 /* Continue every chain from new occupations (occ_dev: C x n, device), e.g. to hand
  * it a configuration found by another heuristic. Trial counters, counts, hash and

@@ -71,7 +71,7 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_energies", "goac_topk_fp64", "goac_chains_create", "goac_chains_destroy",
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
             "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
-            "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run"]
+            "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run", "goac_ga_run"]
 
 
 def load():
@@ -103,6 +103,7 @@ def load():
         "goac_chains_export": ([P, P, P, P], I32),
         "goac_remc_exchange": ([P, I32, P, U64, U64, P, P], I32),
         "goac_ga_generation": ([P, I64, P, P, P, P], I32),
+        "goac_ga_run": ([P, I64, P, P, P, I32, I32], I32),
         "goac_gd_run": ([P, I64, P, I64, C.c_double, P, P], I32),
         "goac_chains_load": ([P, P], I32),
         "goac_hybrid_round": ([P, P, I64, P, P, P], I32),
@@ -240,6 +241,15 @@ class Problem:
         prm = GAParams(seed, generation, n_elite, p_mut)
         self.ctx.check(load().goac_ga_generation(self._h, P, _ptr(pop), _ptr(E), C.byref(prm), _ptr(o)))
         return o
+
+    def ga_run(self, pop, E, seed, generation, generations, n_elite=8, p_mut=0.2, precision=GOAC_MIXED):
+        """`generations` generations (indices generation, generation + 1, ...), each
+        followed by the children's energies; pop (P x n) and E (P) are device
+        tensors updated in place."""
+        P = pop.shape[0]
+        prm = GAParams(seed, generation, n_elite, p_mut)
+        self.ctx.check(load().goac_ga_run(self._h, P, _ptr(pop), _ptr(E), C.byref(prm), generations, precision))
+        return pop, E
 
     def gd_run(self, occ, max_steps=1 << 40, tol=1e-9):
         """Best-swap descent of each row of occ (modified in place, on the device);

@@ -16,7 +16,7 @@ __global__ void k_init(int64_t, int32_t, int32_t, const int32_t*, const int32_t*
 __global__ void k_ga_prep(int64_t, const double*, uint64_t*, int32_t*);
 size_t ga_child_lds(const goac_problem* pb);
 goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
-                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out);
+                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out, const uint32_t* g_dev);
 goac_status anchor_batched(goac_ctx*, goac_chains*, int, uint32_t);
 // rows of every group from its slot permutation (hybrid.hip)
 __global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __restrict__ slot,
@@ -591,8 +591,9 @@ extern "C" goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** 
     return GOAC_OK;
 }
 
-extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
-    if (!ctx) return;
+// The context is freed once the caller has released it and no problem or chain
+// set made on it is left, in whichever order the two happen.
+static void ctx_free(goac_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int q = 0; q < kWsSlots; ++q)
         if (ctx->ws[q]) (void)hipFree(ctx->ws[q]);
@@ -602,6 +603,16 @@ extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
         if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
+}
+
+static void ctx_release_dep(goac_ctx* ctx) {
+    if (--ctx->live == 0 && ctx->released) ctx_free(ctx);
+}
+
+extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
+    if (!ctx || ctx->released) return;
+    ctx->released = true;
+    if (ctx->live == 0) ctx_free(ctx);
 }
 
 extern "C" const char* goac_last_error(const goac_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -809,6 +820,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     }
     // ht beyond M is zero
     if (Mp > M && hipMemsetAsync(d.ht + M, 0, (Mp - M) * 8, sm) != hipSuccess) return bail(GOAC_EHIP);
+    ++ctx->live;
     *out = pb;
     return GOAC_OK;
 }
@@ -817,8 +829,10 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
 // cache, whose blocks only work queued later on the same stream reuses.
 extern "C" void goac_problem_destroy(goac_problem* pb) {
     if (!pb) return;
+    goac_ctx* ctx = pb->ctx;
     problem_free(pb);
     delete pb;
+    ctx_release_dep(ctx);
 }
 
 extern "C" goac_status goac_problem_get_info(const goac_problem* pb, goac_problem_info* out) {
@@ -901,7 +915,8 @@ namespace goac {
 // one generation queued on the context's stream; a roulette-weight failure is
 // or-ed into *err_out (cleared first when zero_err), which the caller reads
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
-                                  const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out) {
+                                  const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,
+                                  const uint32_t* g_dev) {
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || !pop_in || !E_in || !prm || !pop_out || pop_in == pop_out || !(prm->p_mut >= 0.0))
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
@@ -921,7 +936,7 @@ goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* po
     hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, cum, err);
     GOAC_CHECK_LAUNCH(ctx);
     GOAC_TRY(rank_select(ctx, P, E_in, ne, cnt, nullptr, elite, nullptr));
-    GOAC_TRY(ga_children(pb, P, pop_in, cum, elite, ne, prm, pop_out));
+    GOAC_TRY(ga_children(pb, P, pop_in, cum, elite, ne, prm, pop_out, g_dev));
     *err_out = err;
     return GOAC_OK;
 }
@@ -940,8 +955,84 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
                                           const goac_ga_params* prm, uint8_t* pop_out) {
     if (!pb) return GOAC_EINVAL;
     int32_t* err = nullptr;
-    GOAC_TRY(ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err));
+    GOAC_TRY(ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err, nullptr));
     return ga_check_err(pb->ctx, err);
+}
+
+namespace {
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+__global__ void k_add_u32(uint32_t* p, uint32_t v) { *p += v; }
+}  // namespace
+
+// Many generations, each followed by the children's energies. The first runs on
+// the stream (it sizes the workspaces); then kGaGraphGens generations at a time
+// are captured once as a graph and replayed, the generation index read from a
+// device counter that the graph's last node advances; the rest run on the stream.
+// The roulette flag of all generations is read once at the end.
+constexpr int32_t kGaGraphGens = 8;   // even, so each replay starts on the same buffer
+
+extern "C" goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop, double* E, const goac_ga_params* prm,
+                                   int32_t generations, int32_t precision) {
+    if (!pb) return GOAC_EINVAL;
+    goac_ctx* ctx = pb->ctx;
+    if (!prm || !pop || !E || P <= 0 || generations < 0 || (precision != GOAC_FP64 && precision != GOAC_MIXED))
+        return fail(ctx, GOAC_EINVAL, "ga_run: bad arguments");
+    if (generations == 0) return GOAC_OK;
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = ctx->stream;
+    if (!ctx->cap) GOAC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    // the second population and the generation counter
+    const size_t b_pop = round_up(P * pb->d.n, 256);
+    size_t bytes = b_pop + 256;
+    void* buf = nullptr;
+    GOAC_TRY(pool_get(ctx, &bytes, &buf));
+    uint8_t* bufs[2] = {pop, (uint8_t*)buf};
+    uint32_t* g_dev = (uint32_t*)((char*)buf + b_pop);
+    int32_t* err = nullptr;
+    const goac_precision pr = (goac_precision)precision;
+    // generation k reads bufs[k & 1] and writes bufs[(k + 1) & 1]
+    auto gen = [&](int32_t k, const uint32_t* gd, uint32_t g) -> goac_status {
+        goac_ga_params gp = *prm;
+        gp.generation = g;
+        GOAC_TRY(ga_generation_enqueue(pb, P, bufs[k & 1], E, &gp, bufs[(k + 1) & 1], k == 0, &err, gd));
+        return goac_energies(pb, P, bufs[(k + 1) & 1], pr, E);
+    };
+    goac_status st = gen(0, nullptr, prm->generation);
+    int32_t k = 1;
+    hipError_t ec = hipSuccess;
+    // the graph lives until the stream has finished its launches
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (st == GOAC_OK && generations - 1 >= 2 * kGaGraphGens) {
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, sm, g_dev, prm->generation + 1u);
+        ctx->stream = ctx->cap;
+        ctx->capturing = true;
+        ec = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal);
+        if (ec == hipSuccess) {
+            for (int32_t q = 0; q < kGaGraphGens && st == GOAC_OK; ++q) st = gen(k + q, g_dev, (uint32_t)q);
+            if (st == GOAC_OK) hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(1), 0, ctx->cap, g_dev, (uint32_t)kGaGraphGens);
+            const hipError_t ee = hipStreamEndCapture(ctx->cap, &graph);
+            if (ec == hipSuccess) ec = ee;
+        }
+        ctx->stream = sm;
+        ctx->capturing = false;
+        if (st == GOAC_OK && ec == hipSuccess) ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        for (; st == GOAC_OK && ec == hipSuccess && k + kGaGraphGens <= generations; k += kGaGraphGens)
+            ec = hipGraphLaunch(exec, sm);
+    }
+    for (; st == GOAC_OK && ec == hipSuccess && k < generations; ++k) st = gen(k, nullptr, prm->generation + (uint32_t)k);
+    if (st == GOAC_OK && ec == hipSuccess && (generations & 1))
+        ec = hipMemcpyAsync(pop, bufs[1], (size_t)(P * pb->d.n), hipMemcpyDeviceToDevice, sm);
+    if (st == GOAC_OK && ec == hipSuccess) st = ga_check_err(ctx, err);   // synchronises
+    if (exec) {
+        (void)hipStreamSynchronize(sm);   // also after an error: no launch of it may be pending
+        (void)hipGraphExecDestroy(exec);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    pool_put(ctx, buf, bytes);
+    if (st != GOAC_OK) return st;
+    if (ec != hipSuccess) return fail(ctx, GOAC_EHIP, std::string("ga_run: graph: ") + hipGetErrorString(ec));
+    return GOAC_OK;
 }
 
 // ------------------------------------------------------------------ chains
@@ -1108,6 +1199,7 @@ extern "C" goac_status goac_chains_create(goac_problem* pb, int64_t C, const uin
         delete ch;
         return st;
     }
+    ++ctx->live;
     *out = ch;
     return GOAC_OK;
 }
@@ -1152,14 +1244,17 @@ extern "C" goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_
         delete ch;
         return st;
     }
+    ++ctx->live;
     *out = ch;
     return GOAC_OK;
 }
 
 extern "C" void goac_chains_destroy(goac_chains* ch) {
     if (!ch) return;
+    goac_ctx* ctx = ch->ctx;
     chains_free(ch);
     delete ch;
+    ctx_release_dep(ctx);
 }
 
 extern "C" goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows) {
@@ -1550,7 +1645,10 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
         }
     }
     if (st == GOAC_OK && ec == hipSuccess) ec = hipStreamSynchronize(sm);
-    if (exec) (void)hipGraphExecDestroy(exec);
+    if (exec) {
+        (void)hipStreamSynchronize(sm);   // also after an error: no launch of it may be pending
+        (void)hipGraphExecDestroy(exec);
+    }
     if (graph) (void)hipGraphDestroy(graph);
     if (st != GOAC_OK) return st;
     if (ec != hipSuccess) return fail(ctx, GOAC_EHIP, std::string("remc_run: graph: ") + hipGetErrorString(ec));

@@ -181,6 +181,8 @@ struct goac_ctx {
     bool stage_pending[2] = {false, false};
     bool capturing = false;  // a stream capture is open on the context's work
     hipStream_t cap = nullptr;  // private stream that graph captures record on (created on first use)
+    int64_t live = 0;           // problems and chain sets not yet destroyed
+    bool released = false;      // goac_ctx_destroy has been called
 };
 
 struct goac_problem {
@@ -309,7 +311,8 @@ void pool_put(goac_ctx* ctx, void* p, size_t bytes);
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
-                                  const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out);
+                                  const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,
+                                  const uint32_t* g_dev = nullptr);
 goac_status ga_check_err(goac_ctx* ctx, const int32_t* err);
 goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, int32_t* cnt_scratch,
                         int64_t* idx64, int32_t* idx32, double* Eout);

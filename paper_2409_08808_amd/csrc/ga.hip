@@ -394,9 +394,11 @@ __global__ __launch_bounds__(64) void k_ga_child(
     const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob,
     const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ, int64_t P,
     const uint8_t* __restrict__ pop_in, const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite,
-    int32_t n_elite, uint64_t seed, uint32_t g, double p_mut, uint8_t* __restrict__ pop_out) {
+    int32_t n_elite, uint64_t seed, uint32_t g, const uint32_t* __restrict__ g_dev, double p_mut,
+    uint8_t* __restrict__ pop_out) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int64_t c = blockIdx.x;
+    if (g_dev) g += *g_dev;   // a captured generation: the index is base + offset
     const int lane = threadIdx.x;
     uint8_t* out = pop_out + c * n;
     if (c < n_elite) {
@@ -532,7 +534,7 @@ size_t ga_child_lds(const goac_problem* pb) {
 }
 
 goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
-                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out) {
+                        int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out, const uint32_t* g_dev) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const bool reg = ga_reg_walk(pb);
@@ -542,7 +544,7 @@ goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, cons
     auto launch = reg ? k_ga_child<true> : k_ga_child<false>;
     hipLaunchKernelGGL(launch, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
                        pb->spos_inv, d.msub, d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite,
-                       n_elite, prm->seed, prm->generation, prm->p_mut, pop_out);
+                       n_elite, prm->seed, prm->generation, g_dev, prm->p_mut, pop_out);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

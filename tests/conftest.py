@@ -1,3 +1,4 @@
+import gc
 import os
 import sys
 
@@ -16,3 +17,11 @@ def pytest_configure(config):
 def pytest_collection_modifyitems(config, items):
     # GPU tests run in one process on one device; order them after the CPU tests.
     items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") else 0)
+
+
+@pytest.fixture(autouse=True)
+def _collect_cycles():
+    """Collect reference cycles (frames kept by exception tracebacks) after each
+    test, while module-scoped contexts are still held by their fixtures."""
+    yield
+    gc.collect()

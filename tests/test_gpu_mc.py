@@ -372,6 +372,33 @@ def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups):
 
 # ------------------------------------------------------------------ GA
 
+@pytest.mark.parametrize("P,prec,gens", [(203, 1, 21), (64, 0, 5), (128, 0, 17), (96, 1, 18)])
+def test_ga_run_matches_generation_by_generation(ctx, cfg2, P, prec, gens):
+    """goac_ga_run (graph replays of eight generations after the first, the rest on
+    the stream) equals goac_ga_generation + goac_energies called generation by
+    generation, bit for bit; a second call (captured again) after eager work too.
+    The single generations are pinned to the oracle elsewhere."""
+    cell, V = cfg2
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    pop0 = pb.init_occupations(P, seed=P)
+    E0 = pb.energies(pop0, prec)
+    pa, Ea = pop0.clone(), E0.clone()
+    pbk, Eb = pop0.clone(), E0.clone()
+    g0 = 3
+    for call in range(2):
+        pb.ga_run(pa, Ea, seed=17, generation=g0, generations=gens, n_elite=4, p_mut=0.3, precision=prec)
+        for k in range(gens):
+            child = pb.ga_generation(pbk, Eb, seed=17, generation=g0 + k, n_elite=4, p_mut=0.3)
+            Eb = pb.energies(child, prec)
+            pbk = child
+        assert torch.equal(pa, pbk), "populations differ (call %d)" % call
+        assert torch.equal(Ea, Eb), "energies differ (call %d)" % call
+        g0 += gens
+        pb.energies(pop0, 0)                      # eager work between the calls
+        torch.cuda.synchronize()
+    pb.close()
+
+
 def test_ga_generation_reports_roulette_overflow(ctx, cfg1):
     """An energy spread beyond the integer roulette weights' range is an error
     (set from the host, the kernels run normally); the next call starts clean."""
