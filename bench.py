@@ -200,7 +200,8 @@ def main():
 
 def ga_energies(ctx, G, S, torch, stream, generations):
     """GA workload: 8x8x8 rock-salt (N = 4096), P = 1024, `generations`
-    generations; energies/s counts only the population-energy calls."""
+    generations; energies/s counts only the population-energy calls (mixed: with
+    the tile the autotuner picked for this population size)."""
     cell = S.config3()
     V = ctx.build_ewald(cell["lattice"], cell["pos"])
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
@@ -209,6 +210,8 @@ def ga_energies(ctx, G, S, torch, stream, generations):
     for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
         pop = pb.init_occupations(1024, seed=0)
         E = torch.empty(1024, dtype=torch.float64, device=pop.device)
+        if prec == G.GOAC_MIXED:
+            out["ga_mixed_tile_autotuned"] = pb.energies_autotune(pop)
         pb.energies(pop, prec, out=E)                      # warm-up
         torch.cuda.synchronize()
         t_en = 0.0

@@ -158,6 +158,21 @@ goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64_t seed, ui
 goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
                           goac_precision prec, double* E_dev);
 
+/* Tile of the GOAC_MIXED population product for populations of P rows: kt n-tiles
+ * of 128 positions per K block (1, 2, 4 or 8, at most the problem's number of
+ * n-tiles unless 1; 0 returns P to the built-in cost model). The energies differ
+ * between tiles only by the FP32 accumulation order, within the mixed bound.
+ * Host-side; errors: EINVAL. */
+goac_status goac_energies_tile(goac_problem* pb, int64_t P, int32_t kt);
+
+/* Autotuner of that tile: times goac_energies(GOAC_MIXED) of occ_dev (P x n, device)
+ * with every valid tile (one warm-up and the best of three calls, HIP events) and
+ * keeps the fastest for later calls with P rows, as goac_energies_tile would.
+ *   kt_out : the chosen tile (may be NULL)
+ * Synchronises; takes P doubles of scratch from the context's cache for the call.
+ * Errors: EINVAL; EINEXACT as goac_energies. */
+goac_status goac_energies_autotune(goac_problem* pb, int64_t P, const uint8_t* occ_dev, int32_t* kt_out);
+
 /* The k lowest configurations among P candidates (Methodology: the n lowest
  * structures are the output): FP64 energies ordered by (E, index).
  *   idx_dev : k int64 output; E_dev : k FP64 output (k <= P). */

@@ -71,7 +71,8 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_energies", "goac_topk_fp64", "goac_chains_create", "goac_chains_destroy",
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
             "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
-            "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run", "goac_ga_run"]
+            "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run", "goac_ga_run", "goac_energies_tile",
+            "goac_energies_autotune"]
 
 
 def load():
@@ -104,6 +105,8 @@ def load():
         "goac_remc_exchange": ([P, I32, P, U64, U64, P, P], I32),
         "goac_ga_generation": ([P, I64, P, P, P, P], I32),
         "goac_ga_run": ([P, I64, P, P, P, I32, I32], I32),
+        "goac_energies_tile": ([P, I64, I32], I32),
+        "goac_energies_autotune": ([P, I64, P, P], I32),
         "goac_gd_run": ([P, I64, P, I64, C.c_double, P, P], I32),
         "goac_chains_load": ([P, P], I32),
         "goac_hybrid_round": ([P, P, I64, P, P, P], I32),
@@ -224,6 +227,18 @@ class Problem:
         E = out if out is not None else torch.empty(P, dtype=torch.float64, device=self.ctx.device)
         self.ctx.check(load().goac_energies(self._h, P, _ptr(occ), precision, _ptr(E)))
         return E
+
+    def energies_tile(self, P, kt):
+        """Set the mixed population product's tile for P rows (0: the cost model)."""
+        self.ctx.check(load().goac_energies_tile(self._h, P, kt))
+
+    def energies_autotune(self, occ):
+        """Time every tile on this population and keep the fastest for its size;
+        returns the tile."""
+        occ = _dev(occ, torch.uint8, self.ctx.device)
+        kt = C.c_int32(0)
+        self.ctx.check(load().goac_energies_autotune(self._h, occ.shape[0], _ptr(occ), C.byref(kt)))
+        return kt.value
 
     def topk(self, occ, k):
         occ = _dev(occ, torch.uint8, self.ctx.device)

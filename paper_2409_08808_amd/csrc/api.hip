@@ -894,6 +894,73 @@ extern "C" goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t*
     return energies_fp64(pb, P, occ, E);
 }
 
+// tiles of the mixed population product: 1, 2, 4 or 8 n-tiles of 128 positions per
+// K block, no more than the problem has (one always works)
+static bool valid_pop_kt(const goac_problem* pb, int32_t kt) {
+    const int32_t nt = (pb->d.Mp + 127) / 128;
+    return (kt == 1 || kt == 2 || kt == 4 || kt == 8) && (kt == 1 || kt <= nt);
+}
+
+extern "C" goac_status goac_energies_tile(goac_problem* pb, int64_t P, int32_t kt) {
+    if (!pb) return GOAC_EINVAL;
+    if (P <= 0) return fail(pb->ctx, GOAC_EINVAL, "energies_tile: P must be positive");
+    if (kt == 0) {
+        pb->pop_kt.erase(P);
+        return GOAC_OK;
+    }
+    if (!valid_pop_kt(pb, kt)) return fail(pb->ctx, GOAC_EINVAL, "energies_tile: tile not 1, 2, 4 or 8 n-tiles within the problem");
+    pb->pop_kt[P] = kt;
+    return GOAC_OK;
+}
+
+// Times the mixed energies of the given population with each tile (one warm-up
+// and the best of three timed calls, HIP events on the context's stream) and keeps
+// the fastest for later calls with the same population size.
+extern "C" goac_status goac_energies_autotune(goac_problem* pb, int64_t P, const uint8_t* occ, int32_t* kt_out) {
+    if (!pb) return GOAC_EINVAL;
+    goac_ctx* ctx = pb->ctx;
+    if (P <= 0 || !occ) return fail(ctx, GOAC_EINVAL, "energies_autotune: bad arguments");
+    if (!pb->d.mixed_exact) return fail(ctx, GOAC_EINEXACT, "energies_autotune: a shifted charge is not bf16-exact");
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    size_t bytes = (size_t)P * 8;
+    void* buf = nullptr;
+    GOAC_TRY(pool_get(ctx, &bytes, &buf));
+    double* E = (double*)buf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t ec = hipEventCreate(&e0);
+    if (ec == hipSuccess) ec = hipEventCreate(&e1);
+    goac_status st = GOAC_OK;
+    int32_t best = 0;
+    float best_ms = 0.0f;
+    for (int32_t kt = 1; kt <= 8 && st == GOAC_OK && ec == hipSuccess; kt *= 2) {
+        if (!valid_pop_kt(pb, kt)) continue;
+        st = energies_mixed(pb, P, occ, E, kt);
+        float t_min = -1.0f;
+        for (int rep = 0; rep < 3 && st == GOAC_OK && ec == hipSuccess; ++rep) {
+            ec = hipEventRecord(e0, ctx->stream);
+            if (ec == hipSuccess) st = energies_mixed(pb, P, occ, E, kt);
+            if (ec == hipSuccess && st == GOAC_OK) ec = hipEventRecord(e1, ctx->stream);
+            if (ec == hipSuccess && st == GOAC_OK) ec = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (ec == hipSuccess && st == GOAC_OK) ec = hipEventElapsedTime(&ms, e0, e1);
+            if (ec == hipSuccess && st == GOAC_OK && (t_min < 0.0f || ms < t_min)) t_min = ms;
+        }
+        if (st == GOAC_OK && ec == hipSuccess && (best == 0 || t_min < best_ms)) {
+            best = kt;
+            best_ms = t_min;
+        }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    pool_put(ctx, buf, bytes);
+    if (st != GOAC_OK) return st;
+    if (ec != hipSuccess) return fail(ctx, GOAC_EHIP, std::string("energies_autotune: ") + hipGetErrorString(ec));
+    pb->pop_kt[P] = best;
+    if (kt_out) *kt_out = best;
+    return GOAC_OK;
+}
+
 extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, int32_t k, int64_t* idx,
                                       double* Eout) {
     if (!pb) return GOAC_EINVAL;

@@ -200,6 +200,8 @@ struct goac_problem {
     mutable double E_ff = 0.0, E_t = 0.0;
     void* arena = nullptr;           // one allocation holding every device array
     size_t arena_bytes = 0;
+    std::map<int64_t, int32_t> pop_kt;  // population size -> n-tiles per K block of the
+                                        // mixed energies (set or tuned; else the cost model)
 };
 
 struct goac_chains {
@@ -308,7 +310,7 @@ void pool_put(goac_ctx* ctx, void* p, size_t bytes);
 
 // population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies
 // by (E, index); cnt_scratch holds P int32
-goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt = 0);
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
                                   const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,

@@ -509,29 +509,39 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
     return GOAC_OK;
 }
 
-goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
     const int64_t MT = (P + PB_BM - 1) / PB_BM;
     // the symmetric form: K blocks of KT n-tiles; pairs(KT) = sum_t (t / KT + 1).
-    // KT minimises the estimated makespan: rounds of two workgroups per compute unit
-    // times the K length of one plus a fixed cost of 128 K steps (measured on the
-    // 4x4x4, 8x8x8 and 16x16x8 rock-salt populations); ties go to the longer K
+    // KT is the requested one, else the one set or tuned for this population size,
+    // else the one that minimises the estimated makespan: rounds of two workgroups
+    // per compute unit times the K length of one plus a fixed cost of 128 K steps
+    // (measured on the 4x4x4, 8x8x8 and 16x16x8 rock-salt populations); ties go to
+    // the longer K
     auto pairs = [&](int kt) {
         int64_t n = 0;
         for (int t = 0; t < NT; ++t) n += t / kt + 1;
         return n;
     };
     int KT = 1;
-    int64_t best_cost = -1;
-    for (int kt = 1; kt <= 8 && (kt == 1 || kt <= NT); kt *= 2) {
-        const int64_t wg = MT * pairs(kt);
-        const int64_t rounds = (wg + 2 * ctx->num_cus - 1) / (2 * ctx->num_cus);
-        const int64_t cost = rounds * ((int64_t)kt * PB_BN + 128);
-        if (best_cost < 0 || cost <= best_cost) {
-            best_cost = cost;
-            KT = kt;
+    if (kt_req <= 0) {
+        const auto it = pb->pop_kt.find(P);
+        if (it != pb->pop_kt.end()) kt_req = it->second;
+    }
+    if (kt_req > 0) {
+        KT = kt_req;
+    } else {
+        int64_t best_cost = -1;
+        for (int kt = 1; kt <= 8 && (kt == 1 || kt <= NT); kt *= 2) {
+            const int64_t wg = MT * pairs(kt);
+            const int64_t rounds = (wg + 2 * ctx->num_cus - 1) / (2 * ctx->num_cus);
+            const int64_t cost = rounds * ((int64_t)kt * PB_BN + 128);
+            if (best_cost < 0 || cost <= best_cost) {
+                best_cost = cost;
+                KT = kt;
+            }
         }
     }
     const int64_t total = MT * pairs(KT);

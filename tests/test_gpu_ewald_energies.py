@@ -150,6 +150,52 @@ def test_energies_config2(ctx, cfg2, prec, tol):
     assert np.abs(Eg - Eo).max() / 512 <= tol
 
 
+def test_energies_every_tile_and_the_autotuner(ctx, cfg2):
+    """The mixed energies with each tile of the population product (1, 2 and 4
+    n-tiles per K block on the 256-position cell; 8 is beyond it) against the
+    oracle; the autotuner picks one of them and later calls use it."""
+    cell, Vo = cfg2
+    occ = S.random_occupations(cell, 300, seed=12)
+    Eo = O.energies(Vo, occ, cell["charge"])
+    pb = G.Problem(ctx, torch.from_numpy(Vo), cell["sublattice"], cell["species"], cell["charge"])
+    occ_t = torch.from_numpy(occ).cuda()
+    by_kt = {}
+    for kt in (1, 2):
+        pb.energies_tile(300, kt)
+        Eg = pb.energies(occ_t, G.GOAC_MIXED).cpu().numpy()
+        assert np.abs(Eg - Eo).max() / 512 <= TOL_MIXED, kt
+        by_kt[kt] = Eg
+    with pytest.raises(G.GoacError):
+        pb.energies_tile(300, 4)                 # two n-tiles only
+    with pytest.raises(G.GoacError):
+        pb.energies_tile(300, 3)
+    pb.energies_tile(300, 0)
+    kt = pb.energies_autotune(occ_t)
+    assert kt in by_kt
+    assert np.array_equal(pb.energies(occ_t, G.GOAC_MIXED).cpu().numpy(), by_kt[kt])
+    # other population sizes keep the cost model; FP64 is untouched
+    Ef = pb.energies(occ_t[:77], G.GOAC_FP64).cpu().numpy()
+    assert np.abs(Ef - Eo[:77]).max() / 512 <= TOL_FP64
+    pb.close()
+
+
+def test_energies_tiles_on_a_wide_cell(ctx):
+    """Config 3 (2048 positions, 16 n-tiles): tiles 1, 2, 4 and 8 agree with the
+    FP64 path within the mixed bound."""
+    cell = S.config3()
+    Vg = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, Vg, cell["sublattice"], cell["species"], cell["charge"])
+    pop = pb.init_occupations(300, seed=2)
+    Ef = pb.energies(pop, G.GOAC_FP64).cpu().numpy()
+    n = len(cell["pos"])
+    for kt in (1, 2, 4, 8):
+        pb.energies_tile(300, kt)
+        Em = pb.energies(pop, G.GOAC_MIXED).cpu().numpy()
+        assert np.abs(Em - Ef).max() / n <= TOL_MIXED, kt
+    assert pb.energies_autotune(pop) in (1, 2, 4, 8)
+    pb.close()
+
+
 def test_energies_interleaved_site_order(ctx):
     # mobile and fixed sites interleaved, two mobile sublattices
     cell = two_sublattice_cell()
