@@ -37,9 +37,9 @@ BF16_PEAK = 2.5e15
 # HBM bytes of one k_mc<mixed, 64> launch of this step from FETCH_SIZE and WRITE_SIZE,
 # each scaled by the same counter's reading for a 256 MiB copy (factors 2.0 and 1.0);
 # valid only for the kernel sources they were taken on (profiles/k_mc_rocksalt4x4x4_traffic.md)
-MC_TRAFFIC = {"bytes": 71907050.0,
+MC_TRAFFIC = {"bytes": 71340261.0,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": "e8931456bc7ff8fd3ff2c69b48493dd9fcfb26311bb20d2762a21bb83a90862b"}
+              "sha256": "07ff82851e70f93dbe519dbbe92f83c16e0c3c21ad04d00908c46e1aaf5121a6"}
 
 
 def parse():
