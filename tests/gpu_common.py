@@ -39,3 +39,20 @@ def swap_energy_difference(Vi, Vj, q, i, j):
     q2[i], q2[j] = q[j], q[i]
     s = q + q2
     return 0.5 * ((q2[i] - q[i]) * (Vi @ s) + (q2[j] - q[j]) * (Vj @ s))
+
+
+def degenerate_sublattice_cell():
+    """Config-1 geometry with the 16 cation positions split into two sublattices:
+    eight hold Mg2+ only (no swap there has a valid partner) and eight hold four
+    Li+ and four M3+; 16 fixed O2-; total charge 16 + 16 - 32 = 0."""
+    lat, pos, kind = S.rocksalt_conventional(2, 2, 1, 4.2)
+    names = ["O", "Li", "M", "Mg"]
+    charge = [-2.0, 1.0, 3.0, 2.0]
+    cat = np.nonzero(kind == 0)[0]
+    sub = np.full(len(pos), -1, np.int32)
+    sub[cat[:8]] = 0
+    sub[cat[8:]] = 1
+    spc = np.zeros(len(pos), np.uint8)
+    spc[cat[:8]] = 3
+    spc[cat[8:]] = np.array([1, 2] * 4, np.uint8)
+    return S.make_cell(lat, pos, sub, spc, charge, names)

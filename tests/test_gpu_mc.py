@@ -10,7 +10,7 @@ import torch
 
 import oracle as O
 import supercells as S
-from gpu_common import many_species_cell, two_sublattice_cell
+from gpu_common import degenerate_sublattice_cell, many_species_cell, two_sublattice_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -121,6 +121,32 @@ def test_mc_frequent_accepts(ctx, which, kT, prec, variant):
     occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 3000, [kT], 10 ** 9, 5, reanchor=64, variant=variant)
     _compare(cell, stats, occ, best, st, prec, V)
     assert stats["accepts"].sum() > 0.01 * 24 * 3000
+
+
+@pytest.mark.parametrize("block_len", [7, 200])
+@pytest.mark.parametrize("prec,variant", [(0, 64), (1, 64), (1, 256)])
+def test_mc_degenerate_cell_and_temperature_extremes(ctx, prec, variant, block_len):
+    """Edge cases against the oracle: a sublattice without a valid swap partner
+    (its trials are rejected without a pick), temperatures below the FP32 filter's
+    range (every trial is decided by the exact rule) and far above the energy
+    scale, blocks shorter than a window (each lane finds its own temperature), and
+    a trial count that ends inside a window. Near zero temperature a trial is
+    accepted iff dE <= 0, and swaps that change nothing physically have dE = 0 up
+    to the rounding of the field, whose summation order differs between the two
+    sides; a symmetric integer pair matrix makes every field and dE exact, so the
+    decisions are the same numbers on both sides."""
+    cell = degenerate_sublattice_cell()
+    n = len(cell["pos"])
+    A = np.random.default_rng(3).integers(-4, 5, size=(n, n)).astype(np.float64)
+    V = np.triu(A) + np.triu(A, 1).T
+    kT = [1e-200, 1e6, 0.05, 1e-200, 2.0]
+    occ0 = O.init_occupations(cell, 24, seed=9)
+    st = _run_oracle(cell, V, occ0, 1001, kT, block_len, 9)
+    occ, best, stats = _run_gpu(ctx, cell, V, occ0, prec, 1001, kT, block_len, 9, reanchor=32, variant=variant)
+    _compare(cell, stats, occ, best, st, prec, V)
+    assert np.all(stats["t"] == 1001)
+    sub = cell["sublattice"]
+    assert np.array_equal(occ[:, sub == 0], occ0[:, sub == 0])     # nothing moves there
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -396,6 +422,30 @@ def test_ga_run_matches_generation_by_generation(ctx, cfg2, P, prec, gens):
         g0 += gens
         pb.energies(pop0, 0)                      # eager work between the calls
         torch.cuda.synchronize()
+    pb.close()
+
+
+def test_tiny_populations(ctx, cfg1):
+    """P = 0 and P = 1 energies, top-k of all candidates, and a generation of a
+    one-member population (zero roulette weight: the uniform pick)."""
+    cell, V = cfg1
+    pb = G.Problem(ctx, torch.from_numpy(V), cell["sublattice"], cell["species"], cell["charge"])
+    n = len(cell["pos"])
+    for prec in (G.GOAC_FP64, G.GOAC_MIXED):
+        assert pb.energies(torch.zeros((0, n), dtype=torch.uint8), prec).numel() == 0
+    pop = O.init_occupations(cell, 5, seed=4)
+    Eo = O.energies(V, pop, cell["charge"])
+    for prec, tol in ((G.GOAC_FP64, 1e-6), (G.GOAC_MIXED, 1e-4)):
+        E1 = pb.energies(torch.from_numpy(pop[:1]), prec).cpu().numpy()
+        assert abs(E1[0] - Eo[0]) / n <= tol
+    idx, Ek = pb.topk(torch.from_numpy(pop), 5)
+    idx_o, Ek_o = O.topk(V, pop, cell["charge"], 5)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    assert np.abs(Ek.cpu().numpy() - Ek_o).max() / n <= 1e-6
+    one = pop[:1]
+    got = pb.ga_generation(torch.from_numpy(one), torch.from_numpy(Eo[:1]), seed=2, generation=1, n_elite=0,
+                           p_mut=1.0).cpu().numpy()
+    assert np.array_equal(got, O.ga_generation(cell, one, Eo[:1], seed=2, g=1, n_elite=0, p_mut=1.0))
     pb.close()
 
 
