@@ -473,6 +473,24 @@ def replica_exchange(ctx, G, S, torch, stream):
             out["remc_trial_accept_rate"] = float(st["accepts"].sum()) / (C * rounds * per)
             out["remc_best_E_min"] = float(st["best_E"].min())
     out["remc_trials_per_s"] = out["remc_graph_trials_per_s"]
+    # the same graph rounds with the plain FP64 field (the hot replicas accept about
+    # 40% of their trials, so the mixed field's in-kernel re-anchors recur there)
+    ch = G.Chains(pb, occ0, G.GOAC_FP64)
+    slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
+    ch.autotune(per, float(ladder[0]))
+    ch.remc_run(R, ladder, per, 1, 0, 1, slot.clone())          # warm-up on a copy of the slots
+    ch.close()
+    ch = G.Chains(pb, occ0, G.GOAC_FP64)
+    ch.autotune(per, float(ladder[0]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.remc_run(R, ladder, per, rounds, 0, 1, slot)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ch.close()
+    print("  [remc graph fp64] %.3f s" % sec, file=sys.stderr, flush=True)
+    out["remc_fp64_graph_trials_per_s"] = C * rounds * per / sec
+    out["remc_mixed_vs_fp64"] = out["remc_graph_trials_per_s"] / out["remc_fp64_graph_trials_per_s"]
     pb.close()
     return out
 
