@@ -78,9 +78,9 @@ def algorithmic_ops(trials, updates, M):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the hot path shards chains, instances and "
-              "populations without communication, but this build measures a single "
-              "MI355X only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU: the hot path would shard chains, instances and "
+              "populations without communication, but only a single MI355X is measured "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 
