@@ -277,6 +277,13 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         uint64_t t = sc->t;
         const uint64_t t_end = t + a.n_trials;
         double Ecur = sc->E, best = sc->best_E;
+        bool best_dirty = false;   // occ is the best occupation and gbest not yet updated
+        // occ -> gbest in 32-bit words (M_p is a multiple of 64, both 16-byte aligned)
+        auto copy_best = [&]() {
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(occ);
+            GOAC_GLOBAL uint32_t* dst = reinterpret_cast<GOAC_GLOBAL uint32_t*>(gbest);
+            for (int k = tid; k < Mp / 4; k += WG) dst[k] = src[k];
+        };
         uint64_t n_acc = sc->accepts, n_upd = sc->updates, n_fb = sc->fallbacks, n_anc = sc->anchors;
         double eps = sc->eps;
         float phib = sc->phibound;
@@ -499,6 +506,20 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                         ++n_upd;
                         ++since;
                     }
+                    // the best occupation is copied lazily: only before an accepted swap
+                    // that does not lower the best energy again (or one after which the
+                    // field is re-anchored), and at the end of the launch, so a run of
+                    // improving swaps costs one copy
+                    {
+                        bool anchor_due = false;
+                        if constexpr (MIXED)
+                            anchor_due = bd != 0.0 && a.inline_anchor && since >= (uint32_t)a.reanchor_every;
+                        if (best_dirty && (anchor_due || !(Ecur + bdE < best))) {
+                            copy_best();
+                            best_dirty = false;
+                            __syncthreads();   // the copy reads occ before the swap below
+                        }
+                    }
                     if (tid == 0) {
                         const uint8_t sa = occ[bi], sb = occ[bj];
                         occ[bi] = sb;
@@ -543,7 +564,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                     }
                     if (Ecur < best) {
                         best = Ecur;
-                        for (int k = tid; k < Mp; k += WG) gbest[k] = occ[k];
+                        best_dirty = true;
                     }
                     // the trials after f against the new state: a trial touching i or j
                     // (its species, its partner list) is scored afresh, the others only
@@ -568,6 +589,7 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         }
         // ---- write the chain back
         __syncthreads();
+        if (best_dirty) copy_best();
         for (int k = tid; k < Mp; k += WG) {
             gphi[k] = phi[k];
             gocc[k] = occ[k];
