@@ -1361,12 +1361,13 @@ static goac_status sweep_plan(goac_chains* ch, const goac_mc_params* prm, int wg
     if ((uint64_t)ch->max_Mp * (uint64_t)ch->max_Mp * 8u >= ((uint64_t)1 << 32)) wg = 256;
     const size_t phi_bytes = (size_t)round_up(ch->max_Mp * (mixed ? 4 : 8), 16);
     // occupation, site class (only with several classes), perm and where per
-    // position; one-wave chains add the FP64 diagonal
+    // position; one-wave chains add the FP64 diagonal, multi-wave chains the log
+    // of swaps since the last best-occupation copy
     const bool msub_lds = ch->max_S > 1;
     const size_t lds_base = phi_bytes + (size_t)ch->max_Mp * (1 + (msub_lds ? 1 : 0) + 2 + 2) +
                             round_up(ch->max_tab * 4, 16) + kMaxSpecies * 8;
     if (wg == 64 && lds_base + (size_t)ch->max_Mp * 8 > 160 * 1024) wg = 256;   // no room for it
-    const size_t lds = lds_base + (wg == 64 ? (size_t)ch->max_Mp * 8 : 0);
+    const size_t lds = lds_base + (wg == 64 ? (size_t)ch->max_Mp * 8 : (size_t)kBestLog * 4);
     if (lds > 160 * 1024) return fail(ctx, GOAC_EINVAL, "mc_sweep: the chain state does not fit in LDS");
     const int cap = std::max<int>(1, std::min<int>(wg == 64 ? 16 : 4, (int)((160 * 1024) / lds)));
     const int per_cu = per_cu_req > 0 ? std::min(per_cu_req, cap) : cap;

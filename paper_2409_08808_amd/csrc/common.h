@@ -19,6 +19,7 @@ namespace goac {
 constexpr int kMaxSub = 16;       // sublattices per problem
 constexpr int kMaxSpecies = 32;   // species ids per problem
 constexpr int kPad = 64;          // mobile dimension padded to a multiple of this
+constexpr int kBestLog = 256;     // multi-wave chains: swaps logged between best-occupation copies
 
 enum : uint32_t { TAG_MC = 1, TAG_INIT = 2, TAG_SEL = 3, TAG_X = 4, TAG_MUT = 5, TAG_REMC = 6 };
 

@@ -223,6 +223,8 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
     int32_t* tab = reinterpret_cast<int32_t*>(where + a.Mp_max);
     double* chg = reinterpret_cast<double*>(tab + a.tab_max);
     double* dgl = chg + kMaxSpecies;   // one-wave chains: the diagonal V_kk of the instance
+    // multi-wave chains: the accepted swaps since the last best-occupation copy
+    uint32_t* blog = reinterpret_cast<uint32_t*>(chg + kMaxSpecies);
 
     if (tid == 0) s_flag = 0;
     for (int round = 0;; ++round) {
@@ -278,11 +280,28 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
         const uint64_t t_end = t + a.n_trials;
         double Ecur = sc->E, best = sc->best_E;
         bool best_dirty = false;   // occ is the best occupation and gbest not yet updated
-        // occ -> gbest in 32-bit words (M_p is a multiple of 64, both 16-byte aligned)
+        // occ -> gbest. One-wave chains (small cells) copy all of it in 32-bit words
+        // (M_p is a multiple of 64, both 16-byte aligned). Multi-wave chains log the
+        // accepted swaps since the last copy and write only the positions they
+        // touched; the first copy of a launch, or one after the log overflowed, is
+        // a full one.
+        int blog_n = 0;
+        bool blog_full = true;
         auto copy_best = [&]() {
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(occ);
-            GOAC_GLOBAL uint32_t* dst = reinterpret_cast<GOAC_GLOBAL uint32_t*>(gbest);
-            for (int k = tid; k < Mp / 4; k += WG) dst[k] = src[k];
+            if (NW == 1 || blog_full) {
+                const uint32_t* src = reinterpret_cast<const uint32_t*>(occ);
+                GOAC_GLOBAL uint32_t* dst = reinterpret_cast<GOAC_GLOBAL uint32_t*>(gbest);
+                for (int k = tid; k < Mp / 4; k += WG) dst[k] = src[k];
+            } else {
+                for (int e = tid; e < blog_n; e += WG) {
+                    const uint32_t u = blog[e];
+                    const uint32_t p = u & 0xffffu, q = u >> 16;
+                    gbest[p] = occ[p];
+                    gbest[q] = occ[q];
+                }
+            }
+            blog_n = 0;
+            blog_full = false;
         };
         uint64_t n_acc = sc->accepts, n_upd = sc->updates, n_fb = sc->fallbacks, n_anc = sc->anchors;
         double eps = sc->eps;
@@ -529,6 +548,11 @@ __global__ __launch_bounds__(WG, WG == 64 ? 4 : 2) void k_mc(McArgs a) {
                         perm[wj] = (uint16_t)bi;
                         where[bi] = wj;
                         where[bj] = wi;
+                        if (NW > 1 && blog_n < kBestLog) blog[blog_n] = (uint32_t)bi | ((uint32_t)bj << 16);
+                    }
+                    if constexpr (NW > 1) {
+                        if (blog_n < kBestLog) ++blog_n;
+                        else blog_full = true;
                     }
                     Ecur += bdE;
                     ++n_acc;
