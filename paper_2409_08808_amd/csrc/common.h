@@ -164,6 +164,19 @@ struct McInst {
 
 // ------------------------------------------------------------------ host objects
 constexpr int kWsSlots = 3;   // scratch slots: 0 kernels' operands, 1 GEMM partials, 2 selection
+// host-side tables of the last Ewald build and the inputs they were made from
+struct EwaldPlan {
+    int64_t n = -1;                 // -1: no valid plan
+    double lat[9] = {};
+    std::vector<double> pos;
+    double alpha_in = 0.0, rcut_in = 0.0;
+    int32_t kmax_in = 0;
+    std::vector<char> img;          // fractional | folded positions | translations | G | lattice
+    size_t b_frac = 0, b_pos = 0, b_tr = 0, b_G = 0, b_A = 0;
+    int32_t K = 0, ld = 0, ntrans = 0;
+    double alpha = 0.0, rcut = 0.0, ke = 0.0, cst = 0.0, self = 0.0;
+};
+
 struct goac_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -182,6 +195,7 @@ struct goac_ctx {
     bool stage_pending[2] = {false, false};
     bool capturing = false;  // a stream capture is open on the context's work
     hipStream_t cap = nullptr;  // private stream that graph captures record on (created on first use)
+    EwaldPlan ewald;            // reused by a build of the same cell and parameters
     int64_t live = 0;           // problems and chain sets not yet destroyed
     bool released = false;      // goac_ctx_destroy has been called
 };

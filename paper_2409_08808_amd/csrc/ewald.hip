@@ -109,12 +109,23 @@ __global__ void k_ewald_table(int64_t n, int32_t K, int32_t ld, const double* __
 // CODATA 2018: e = 1.602176634e-19 C, eps0 = 8.8541878128e-12 F/m -> eV A
 static double coulomb_constant() { return 1.602176634e-19 / (4.0 * kPi * 8.8541878128e-12) * 1e10; }
 
-goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const double* pos, const goac_ewald_params* prm,
-                        double* V) {
+// The host-side tables of a build (fractional and folded positions, lattice
+// translations, half-space G vectors with their weights), laid out as uploaded.
+// They depend only on the inputs, so the context keeps the last set and reuses it
+// when the same cell and parameters come again.
+static goac_status ewald_plan(goac_ctx* ctx, const double* lat, int64_t n, const double* pos,
+                              const goac_ewald_params* prm, EwaldPlan& P) {
+    const double alpha_in = prm ? prm->alpha : 0.0, rcut_in = prm ? prm->rcut : 0.0;
+    const int32_t kmax_in = prm ? prm->kmax : 0;
+    if (P.n == n && P.alpha_in == alpha_in && P.rcut_in == rcut_in && P.kmax_in == kmax_in &&
+        std::memcmp(P.lat, lat, sizeof(P.lat)) == 0 && P.pos.size() == (size_t)(3 * n) &&
+        std::memcmp(P.pos.data(), pos, (size_t)(3 * n) * sizeof(double)) == 0)
+        return GOAC_OK;
+    P.n = -1;   // invalid until complete
     Cell c;
     if (!cell_setup(lat, c)) return fail(ctx, GOAC_EINVAL, "build_ewald: singular lattice");
-    double alpha = prm ? prm->alpha : 0.0, rcut = prm ? prm->rcut : 0.0;
-    int kmax = prm ? prm->kmax : 0;
+    double alpha = alpha_in, rcut = rcut_in;
+    int kmax = kmax_in;
     if (!(alpha > 0.0)) alpha = 5.0 / std::cbrt(c.vol);
     if (!(rcut > 0.0)) rcut = 6.0 / alpha;
     if (kmax <= 0) {
@@ -154,6 +165,8 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
                 if (skip) continue;
                 for (int k = 0; k < 3; ++k) trans.push_back(a * c.A[0][k] + b * c.A[1][k] + e * c.A[2][k]);
             }
+    if (trans.size() * sizeof(double) > 60 * 1024)
+        return fail(ctx, GOAC_EINVAL, "build_ewald: real-space cutoff spans too many cells");
     // half-space reciprocal vectors (first non-zero index positive) with weights
     std::vector<double> G;
     for (int a = -kmax; a <= kmax; ++a)
@@ -167,54 +180,72 @@ goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const doubl
                 const double w = 2.0 * (4.0 * kPi / c.vol) * std::exp(-g2 / (4.0 * alpha * alpha)) / g2;
                 G.insert(G.end(), {g[0], g[1], g[2], std::sqrt(ke * w)});
             }
-    const int32_t K = (int32_t)(G.size() / 4);
-    const int32_t ld = (int32_t)round_up(2 * (int64_t)std::max(K, 1), 16);
-
-    const size_t b_frac = round_up(frac.size() * 8, 256), b_pos = round_up(3 * n * 8, 256);
-    const size_t b_tr = round_up(trans.size() * 8 + 8, 256), b_G = round_up(G.size() * 8 + 8, 256);
-    const size_t b_A = 256, b_T = (size_t)n * ld * 8;
-    void* ws = nullptr;
-    goac_status st = workspace(ctx, 0, b_frac + b_pos + b_tr + b_G + b_A + b_T, &ws);
-    if (st != GOAC_OK) return st;
-    char* p = (char*)ws;
-    double* d_frac = (double*)p; p += b_frac;
-    double* d_pos = (double*)p; p += b_pos;
-    double* d_tr = (double*)p; p += b_tr;
-    double* d_G = (double*)p; p += b_G;
-    double* d_A = (double*)p; p += b_A;
-    double* d_T = (double*)p;
+    P.K = (int32_t)(G.size() / 4);
+    P.ld = (int32_t)round_up(2 * (int64_t)std::max(P.K, 1), 16);
+    P.ntrans = (int32_t)(trans.size() / 3);
+    P.b_frac = round_up(frac.size() * 8, 256);
+    P.b_pos = round_up(3 * n * 8, 256);
+    P.b_tr = round_up(trans.size() * 8 + 8, 256);
+    P.b_G = round_up(G.size() * 8 + 8, 256);
+    P.b_A = 256;
     // folded Cartesian positions for the tables (exact phase equivalence mod 2 pi)
     std::vector<double> cpos(3 * n);
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
             cpos[3 * i + k] = frac[3 * i] * c.A[0][k] + frac[3 * i + 1] * c.A[1][k] + frac[3 * i + 2] * c.A[2][k];
     // the tables in the workspace's layout, one copy
-    std::vector<char> img(b_frac + b_pos + b_tr + b_G + b_A, 0);
-    std::memcpy(img.data(), frac.data(), frac.size() * 8);
-    std::memcpy(img.data() + b_frac, cpos.data(), cpos.size() * 8);
-    if (!trans.empty()) std::memcpy(img.data() + b_frac + b_pos, trans.data(), trans.size() * 8);
-    if (!G.empty()) std::memcpy(img.data() + b_frac + b_pos + b_tr, G.data(), G.size() * 8);
-    std::memcpy(img.data() + b_frac + b_pos + b_tr + b_G, &c.A[0][0], 9 * 8);
-    GOAC_TRY(upload(ctx, d_frac, img.data(), img.size()));
-    const double cst = -ke * kPi / (c.vol * alpha * alpha);
-    const double self = ke * 2.0 * alpha / std::sqrt(kPi);
+    P.img.assign(P.b_frac + P.b_pos + P.b_tr + P.b_G + P.b_A, 0);
+    std::memcpy(P.img.data(), frac.data(), frac.size() * 8);
+    std::memcpy(P.img.data() + P.b_frac, cpos.data(), cpos.size() * 8);
+    if (!trans.empty()) std::memcpy(P.img.data() + P.b_frac + P.b_pos, trans.data(), trans.size() * 8);
+    if (!G.empty()) std::memcpy(P.img.data() + P.b_frac + P.b_pos + P.b_tr, G.data(), G.size() * 8);
+    std::memcpy(P.img.data() + P.b_frac + P.b_pos + P.b_tr + P.b_G, &c.A[0][0], 9 * 8);
+    P.alpha = alpha;
+    P.rcut = rcut;
+    P.ke = ke;
+    P.cst = -ke * kPi / (c.vol * alpha * alpha);
+    P.self = ke * 2.0 * alpha / std::sqrt(kPi);
+    // the key, last
+    std::memcpy(P.lat, lat, sizeof(P.lat));
+    P.pos.assign(pos, pos + 3 * n);
+    P.alpha_in = alpha_in;
+    P.rcut_in = rcut_in;
+    P.kmax_in = kmax_in;
+    P.n = n;
+    return GOAC_OK;
+}
+
+goac_status build_ewald(goac_ctx* ctx, const double* lat, int64_t n, const double* pos, const goac_ewald_params* prm,
+                        double* V) {
+    EwaldPlan& P = ctx->ewald;
+    GOAC_TRY(ewald_plan(ctx, lat, n, pos, prm, P));
+    const size_t b_T = (size_t)n * P.ld * 8;
+    void* ws = nullptr;
+    goac_status st = workspace(ctx, 0, P.img.size() + b_T, &ws);
+    if (st != GOAC_OK) return st;
+    char* p = (char*)ws;
+    double* d_frac = (double*)p; p += P.b_frac;
+    double* d_pos = (double*)p; p += P.b_pos;
+    double* d_tr = (double*)p; p += P.b_tr;
+    double* d_G = (double*)p; p += P.b_G;
+    double* d_A = (double*)p; p += P.b_A;
+    double* d_T = (double*)p;
+    GOAC_TRY(upload(ctx, d_frac, P.img.data(), P.img.size()));
     {
-        const size_t lds_tr = trans.size() * sizeof(double);
-        if (lds_tr > 60 * 1024) return fail(ctx, GOAC_EINVAL, "build_ewald: real-space cutoff spans too many cells");
         dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-        hipLaunchKernelGGL(k_ewald_real, grid, dim3(256), lds_tr, ctx->stream, n, d_frac, d_A, d_tr,
-                           (int32_t)(trans.size() / 3), alpha, rcut, ke, cst, self, V);
+        hipLaunchKernelGGL(k_ewald_real, grid, dim3(256), (size_t)P.ntrans * 3 * sizeof(double), ctx->stream, n,
+                           d_frac, d_A, d_tr, P.ntrans, P.alpha, P.rcut, P.ke, P.cst, P.self, V);
         GOAC_CHECK_LAUNCH(ctx);
     }
-    if (K > 0) {
-        const int64_t tot = n * (int64_t)ld / 2;
-        hipLaunchKernelGGL(k_ewald_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, n, K, ld,
-                           d_pos, d_G, d_T);
+    if (P.K > 0) {
+        const int64_t tot = n * (int64_t)P.ld / 2;
+        hipLaunchKernelGGL(k_ewald_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, n, P.K,
+                           P.ld, d_pos, d_G, d_T);
         GOAC_CHECK_LAUNCH(ctx);
-        st = dgemm_nt(ctx, n, n, ld, d_T, ld, d_T, ld, V, n, 1.0, 1.0, nullptr, true);
+        st = dgemm_nt(ctx, n, n, P.ld, d_T, P.ld, d_T, P.ld, V, n, 1.0, 1.0, nullptr, true);
         if (st != GOAC_OK) return st;
     }
-    // the uploads came from the staging ring, so the host vectors may go now
+    // the uploads came from the staging ring, so the host tables may change now
     return GOAC_OK;
 }
 
