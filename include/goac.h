@@ -60,7 +60,8 @@ typedef struct goac_chains goac_chains;
 goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** out);
 /* Release the context. Its memory is freed (after waiting for its stream) once
  * every problem and chain set made on it has been destroyed too, so these may be
- * destroyed before or after the context; no other call may use it afterwards. */
+ * destroyed before or after the context; no other call may use it afterwards, and
+ * the borrowed stream must stay valid until the last of them is destroyed. */
 void goac_ctx_destroy(goac_ctx* ctx);
 /* Message of the last failed call on ctx; valid until the next call on ctx. */
 const char* goac_last_error(const goac_ctx* ctx);
