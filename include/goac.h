@@ -324,7 +324,9 @@ typedef struct {
  *               of Philox at counter (position, c, g, 4))
  *   mutation  : with probability p_mut one valid swap (Philox at (c, g, 1, 5))
  *   pop_in_dev : P x n; E_in_dev : P FP64; pop_out_dev : P x n (not aliasing pop_in).
- * Errors: EINVAL, also if (E_max - E_min) 2^30 P exceeds 2^62. */
+ * Errors: EINVAL, also if (E_max - E_min) 2^30 P exceeds 2^62 (or an energy is
+ * not a number): the weights are checked before any child is formed, the host
+ * waiting for them, and pop_out_dev is then left untouched. */
 goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
@@ -350,7 +352,8 @@ goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop_dev, double* E
  * temperature rows are kept; the position lists, field and energy are rebuilt
  * (an FP64 anchor); the best energy and occupation are replaced only when the new
  * occupation is strictly lower. Each occupation must keep the problem's
- * composition (EINVAL otherwise; the check synchronises). */
+ * composition (EINVAL otherwise, and the chains are left unchanged; the check
+ * runs first and the host waits for it). */
 goac_status goac_chains_load(goac_chains* ch, const uint8_t* occ_dev);
 
 /* ---------------------------------------------------------------- hybrid REMC + GA */

@@ -980,10 +980,12 @@ extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t
 namespace goac {
 
 // one generation queued on the context's stream; a roulette-weight failure is
-// or-ed into *err_out (cleared first when zero_err), which the caller reads
+// or-ed into *err_out (cleared first when zero_err), which the caller reads, or,
+// with check_first, reported (after a wait for the weights alone) before any
+// child is formed
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
                                   const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,
-                                  const uint32_t* g_dev) {
+                                  const uint32_t* g_dev, bool check_first) {
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || !pop_in || !E_in || !prm || !pop_out || pop_in == pop_out || !(prm->p_mut >= 0.0))
         return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
@@ -1002,6 +1004,7 @@ goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* po
     if (zero_err) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, err, 1);
     hipLaunchKernelGGL(k_ga_prep, dim3(1), dim3(1024), 0, ctx->stream, P, E_in, cum, err);
     GOAC_CHECK_LAUNCH(ctx);
+    if (check_first) GOAC_TRY(ga_check_err(ctx, err));
     GOAC_TRY(rank_select(ctx, P, E_in, ne, cnt, nullptr, elite, nullptr));
     GOAC_TRY(ga_children(pb, P, pop_in, cum, elite, ne, prm, pop_out, g_dev));
     *err_out = err;
@@ -1022,8 +1025,7 @@ extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uin
                                           const goac_ga_params* prm, uint8_t* pop_out) {
     if (!pb) return GOAC_EINVAL;
     int32_t* err = nullptr;
-    GOAC_TRY(ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err, nullptr));
-    return ga_check_err(pb->ctx, err);
+    return ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err, nullptr, true);
 }
 
 namespace {
@@ -1183,15 +1185,27 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
     void* sel = nullptr;
     GOAC_TRY(workspace(ctx, 2, 256, &sel));
     int32_t* err = (int32_t*)sel;
+    // the composition check first: the host waits for nothing queued after it, and
+    // the chains are left untouched when an occupation breaks the composition
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, sm, err, 1);
+    for (int i = 0; i < n_inst; ++i) {
+        const ProblemDev& d = ch->pbs[i]->d;
+        const int64_t Ci = ch->count[i];
+        if (Ci == 0) continue;
+        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)Ci), dim3(256), 0, sm, d.n, d.M, d.S, d.E, d.tab, d.mob,
+                           d.msub, occ + ch->occ_row_off[i], err);
+    }
+    GOAC_CHECK_LAUNCH(ctx);
+    int32_t herr = 0;
+    GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, sm));
+    GOAC_HIP(ctx, hipStreamSynchronize(sm));
+    if (herr) return fail(ctx, GOAC_EINVAL, "chains: an occupation breaks the problem's composition");
     for (int i = 0; i < n_inst; ++i) {
         goac_problem* pb = ch->pbs[i];
         const ProblemDev& d = pb->d;
         const int64_t Ci = ch->count[i];
         if (Ci == 0) continue;
         const uint8_t* occ_i = occ + ch->occ_row_off[i];
-        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)Ci), dim3(256), 0, sm, d.n, d.M, d.S, d.E, d.tab, d.mob,
-                           d.msub, occ_i, err);
         hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)Ci), dim3(64), 0, sm, d.n, d.M, d.Mp, d.S, d.E, d.tab, d.mob,
                            d.msub, occ_i, ch->first_chain[i], ch->d_offs, ch->occ, ch->perm,
                            reload ? nullptr : ch->best, reload ? nullptr : ch->sc, i,
@@ -1213,10 +1227,6 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
                                reload ? 1 : 0, ch->occ, ch->best);
         GOAC_CHECK_LAUNCH(ctx);
     }
-    int32_t herr = 0;
-    GOAC_HIP(ctx, hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, sm));
-    GOAC_HIP(ctx, hipStreamSynchronize(sm));
-    if (herr) return fail(ctx, GOAC_EINVAL, "chains: an occupation breaks the problem's composition");
     return GOAC_OK;
 }
 

@@ -329,7 +329,7 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
                                   const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,
-                                  const uint32_t* g_dev = nullptr);
+                                  const uint32_t* g_dev = nullptr, bool check_first = false);
 goac_status ga_check_err(goac_ctx* ctx, const int32_t* err);
 goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, int32_t* cnt_scratch,
                         int64_t* idx64, int32_t* idx32, double* Eout);
