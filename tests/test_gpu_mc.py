@@ -463,6 +463,12 @@ def test_ga_generation_reports_roulette_overflow(ctx, cfg1):
     got = pb.ga_generation(torch.from_numpy(pop), torch.from_numpy(E), seed=1, generation=0).cpu().numpy()
     ref = O.ga_generation(cell, pop, E, seed=1, g=0)
     assert np.array_equal(got, ref)
+    # a run of generations reports the failure after its last generation
+    E_bad = torch.zeros(64, dtype=torch.float64, device="cuda")
+    E_bad[3] = -1e9
+    with pytest.raises(G.GoacError, match="roulette"):
+        pb.ga_run(torch.from_numpy(pop).cuda(), E_bad, seed=1, generation=0, generations=3,
+                  precision=G.GOAC_FP64)
     pb.close()
 
 
