@@ -4,9 +4,10 @@
 // field phi = h + V_mm q of the configuration live in LDS. A step scores every
 // swap of two positions of one site class holding different species,
 //   dE = d (phi_i - phi_j) + 1/2 d^2 (V_ii + V_jj - 2 V_ij),  d = q_j - q_i,
-// streaming the upper triangle of V_mm row by row (threads over j, so each row is
-// read coalesced): a first pass finds the lowest dE, a second pass the
-// lexicographically first pair (i, j) whose dE lies within tol of it. The step
+// streaming the upper triangle of V_mm row by row (the threads stride over the
+// pairs numbered row by row, so rows are read coalesced and no lane idles): a
+// first pass finds the lowest dE, a second pass the lexicographically first pair
+// (i, j) whose dE lies within tol of it. The step
 // applies that swap with the rank-2 field update; descent stops when the lowest
 // dE is >= -tol or after max_steps swaps.
 #include <climits>
@@ -77,15 +78,26 @@ __global__ __launch_bounds__(kGdThreads) void k_gd(int64_t n, int32_t M, int32_t
         return true;
     };
 
+    // pair (i, i + 1 + r): carry r past the end of row i into the next rows; false
+    // once the rows are exhausted
+    auto next_pair = [&](int& i, int& r) -> bool {
+        while (i < M - 1 && r > M - 2 - i) {
+            r -= M - 1 - i;
+            ++i;
+        }
+        return i < M - 1;
+    };
+
     int64_t st = 0;
     while (st < max_steps) {
-        // pass 1: lowest dE
+        // pass 1: lowest dE. The pairs i < j are numbered row by row and the threads
+        // stride over that numbering, so every lane has a pair in every iteration.
         double lo = INFINITY;
-        for (int i = 0; i < M; ++i)
-            for (int j = i + 1 + tid; j < M; j += kGdThreads) {
-                double dE;
-                if (score(i, j, dE)) lo = fmin(lo, dE);
-            }
+        for (int i = 0, r = tid; next_pair(i, r);) {
+            double dE;
+            if (score(i, i + 1 + r, dE)) lo = fmin(lo, dE);
+            r += kGdThreads;
+        }
 #pragma unroll
         for (int s = 1; s < 64; s <<= 1) lo = fmin(lo, __shfl_xor(lo, s, 64));
         if (lane == 0) s_red[wave] = lo;
@@ -98,14 +110,15 @@ __global__ __launch_bounds__(kGdThreads) void k_gd(int64_t n, int32_t M, int32_t
         // pass 2: lexicographically first pair within tol of the lowest
         const double thr = lo + tol;
         long long key = LLONG_MAX;
-        for (int i = 0; i < M && key == LLONG_MAX; ++i)
-            for (int j = i + 1 + tid; j < M; j += kGdThreads) {
-                double dE;
-                if (score(i, j, dE) && dE <= thr) {
-                    key = (long long)i * M + j;
-                    break;
-                }
+        for (int i = 0, r = tid; next_pair(i, r);) {   // a thread's pairs in order
+            double dE;
+            const int j = i + 1 + r;
+            if (score(i, j, dE) && dE <= thr) {
+                key = (long long)i * M + j;
+                break;
             }
+            r += kGdThreads;
+        }
 #pragma unroll
         for (int s = 1; s < 64; s <<= 1) {
             const long long o = __shfl_xor(key, s, 64);
