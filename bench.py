@@ -421,9 +421,10 @@ def gradient_descent(ctx, G, S, torch, stream):
 def replica_exchange(ctx, G, S, torch, stream):
     """Replica-exchange MC on the 4x4x4 rock-salt cell: 256 groups of 16 replicas on
     a geometric ladder 0.02 -> 0.5 eV, 50 rounds of 2000 trials then one exchange
-    step (mixed field). Timed twice from the same start: rounds replayed from one
-    captured HIP graph (goac_remc_run, after autotuning the launch) and the same
-    rounds launched one call at a time; both after an untimed warm-up round."""
+    step (mixed field). Timed three times from the same start: goac_remc_run
+    launching the rounds on the stream and replaying them from a captured HIP graph
+    (both after autotuning the launch), and the same rounds launched one call at a
+    time from Python; all after an untimed warm-up round."""
     cell = S.config2()
     V = ctx.build_ewald(cell["lattice"], cell["pos"])
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
@@ -437,24 +438,25 @@ def replica_exchange(ctx, G, S, torch, stream):
     ws = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
     wa = torch.zeros(C, dtype=torch.uint8, device=occ0.device)
     wsum = torch.zeros(C, dtype=torch.int64, device=occ0.device)
-    w.remc_run(R, ladder, per, 1, 0, 1, ws)
+    w.remc_run(R, ladder, per, 1, 0, 1, ws, graph=True)
+    w.remc_run(R, ladder, per, 1, 1, 1, ws)
     w.sweep(per, ladder[:, None], per, seed=1)
     w.remc_exchange(R, ladder, 1, 1, ws, wa)
     wsum += wa
     float(wsum.sum().item())
     w.close()
-    for mode in ("graph", "eager"):
+    for mode in ("run", "graph", "eager"):
         ch = G.Chains(pb, occ0, G.GOAC_MIXED)
         ch.set_rows(np.tile(np.arange(R), groups))
         slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
         acc = torch.zeros(C, dtype=torch.uint8, device=occ0.device)
         acc_sum = torch.zeros(C, dtype=torch.int64, device=occ0.device)
-        if mode == "graph":
+        if mode != "eager":
             out["remc_autotune"] = list(ch.autotune(per, float(ladder[0])))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if mode == "graph":
-            ch.remc_run(R, ladder, per, rounds, 0, 1, slot)
+        if mode != "eager":
+            ch.remc_run(R, ladder, per, rounds, 0, 1, slot, graph=(mode == "graph"))
         else:
             for x in range(rounds):
                 ch.sweep(per, ladder[:, None], per, seed=1)
@@ -472,8 +474,30 @@ def replica_exchange(ctx, G, S, torch, stream):
             out["remc_exchange_accept_rate"] = float(acc_sum.sum().item()) / attempts
             out["remc_trial_accept_rate"] = float(st["accepts"].sum()) / (C * rounds * per)
             out["remc_best_E_min"] = float(st["best_E"].min())
-    out["remc_trials_per_s"] = out["remc_graph_trials_per_s"]
-    # the same graph rounds with the plain FP64 field (the hot replicas accept about
+    out["remc_trials_per_s"] = out["remc_run_trials_per_s"]
+    # short rounds (64 trials), where launching is a large part of a round: the
+    # captured graph against the same rounds launched one call at a time
+    short, srounds = 64, 200
+    for mode in ("run", "graph", "eager"):
+        ch = G.Chains(pb, occ0, G.GOAC_MIXED)
+        ch.set_rows(np.tile(np.arange(R), groups))
+        slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode != "eager":
+            ch.remc_run(R, ladder, short, srounds, 0, 1, slot, graph=(mode == "graph"))
+        else:
+            for x in range(srounds):
+                ch.sweep(short, ladder[:, None], short, seed=1)
+                ch.remc_exchange(R, ladder, x, 1, slot)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ch.close()
+        out["remc_short_%s_rounds_per_s" % mode] = srounds / sec
+    print("  [remc short] run %.0f, graph %.0f, eager %.0f rounds/s" % (
+        out["remc_short_run_rounds_per_s"], out["remc_short_graph_rounds_per_s"], out["remc_short_eager_rounds_per_s"]),
+        file=sys.stderr, flush=True)
+    # the same rounds with the plain FP64 field (the hot replicas accept about
     # 40% of their trials, so the mixed field's in-kernel re-anchors recur there)
     ch = G.Chains(pb, occ0, G.GOAC_FP64)
     slot = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device=occ0.device)
@@ -488,9 +512,9 @@ def replica_exchange(ctx, G, S, torch, stream):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     ch.close()
-    print("  [remc graph fp64] %.3f s" % sec, file=sys.stderr, flush=True)
-    out["remc_fp64_graph_trials_per_s"] = C * rounds * per / sec
-    out["remc_mixed_vs_fp64"] = out["remc_graph_trials_per_s"] / out["remc_fp64_graph_trials_per_s"]
+    print("  [remc run fp64] %.3f s" % sec, file=sys.stderr, flush=True)
+    out["remc_fp64_run_trials_per_s"] = C * rounds * per / sec
+    out["remc_mixed_vs_fp64"] = out["remc_run_trials_per_s"] / out["remc_fp64_run_trials_per_s"]
     pb.close()
     return out
 

@@ -207,6 +207,7 @@ goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_t n_instanc
                                      goac_precision prec, goac_chains** out);
 
 #define GOAC_MC_TRACE_HASH 1u   /* accumulate the per-trial trajectory hash */
+#define GOAC_REMC_GRAPH 2u      /* goac_remc_run: replay rounds from a captured HIP graph */
 
 /* Parameters of one sweep. kT_host is a table of n_rows x n_blocks kT values
  * (eV); chain c at trial t uses row r_c (the chain set's temperature row, 0
@@ -294,12 +295,15 @@ goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host
  * temperature of its slot followed by exchange step x0 + r (r = 0 .. rounds-1);
  * the same as alternating goac_mc_sweep (the ladder as an R x 1 table) and
  * goac_remc_exchange, bit for bit. The chains' rows are set from slot_dev first.
- * Up to 8 rounds (the sweep's kernels and the exchange) are captured once as one
- * HIP graph and replayed, the step index read from device memory; the rounds % 8
- * left over launch the same kernels on the stream. Cells whose MIXED field
- * re-anchors between sweep chunks (more than 1024 mobile positions) run the same
- * rounds without capture.
- *   flags : 0 or GOAC_MC_TRACE_HASH;  reanchor_every : as in goac_mc_params
+ * The rounds' kernels are launched on the stream one round after another. With
+ * GOAC_REMC_GRAPH, up to 8 rounds (the sweep's kernels and the exchange) are
+ * instead captured once as one HIP graph and replayed, the step index read from
+ * device memory, and the rounds % 8 left over launch the same kernels on the
+ * stream (on ROCm 7.2 the replay measured slower than the plain launches, even
+ * for 64-trial rounds). Cells whose MIXED field re-anchors between sweep chunks
+ * (more than 1024 mobile positions) always run without capture.
+ *   flags : GOAC_MC_TRACE_HASH and/or GOAC_REMC_GRAPH;  reanchor_every : as in
+ *           goac_mc_params
  *   slot_dev : groups x R int32 (in/out). Synchronises. */
 goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials, uint64_t rounds,
                           uint64_t x0, uint64_t seed, uint32_t flags, int32_t reanchor_every, int32_t* slot_dev);

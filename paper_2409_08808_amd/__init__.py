@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libgoac.so")
 
 GOAC_FP64, GOAC_MIXED = 0, 1
 TRACE_HASH = 1
+REMC_GRAPH = 2
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTNEUTRAL", -5: "EINEXACT",
            -6: "EDRIFT", -7: "ESTATE"}
@@ -359,12 +360,15 @@ class Chains:
         self.ctx.check(load().goac_remc_exchange(self._h, R, kT.ctypes.data_as(C.c_void_p), x, seed,
                                                  _ptr(slot), _ptr(acc)))
 
-    def remc_run(self, R, kT_ladder, trials, rounds, x0, seed, slot, trace=False, reanchor_every=1024):
-        """`rounds` replica-exchange rounds (sweep + exchange step x0 + r), replayed
-        from one captured round; slot is updated in place."""
+    def remc_run(self, R, kT_ladder, trials, rounds, x0, seed, slot, trace=False, reanchor_every=1024,
+                 graph=False):
+        """`rounds` replica-exchange rounds (sweep + exchange step x0 + r), launched
+        round after round or, with graph=True, replayed from a captured graph; slot
+        is updated in place."""
         kT = _np(kT_ladder, np.float64)
+        flags = (TRACE_HASH if trace else 0) | (REMC_GRAPH if graph else 0)
         self.ctx.check(load().goac_remc_run(self._h, R, kT.ctypes.data_as(C.c_void_p), trials, rounds, x0, seed,
-                                            TRACE_HASH if trace else 0, reanchor_every, _ptr(slot)))
+                                            flags, reanchor_every, _ptr(slot)))
 
     def autotune(self, probe_trials=2000, kT=0.05):
         """Pick the fastest launch configuration on a probe sweep (state unchanged);

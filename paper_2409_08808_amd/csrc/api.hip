@@ -1636,18 +1636,20 @@ extern "C" goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const doub
 }
 
 
-// Many replica-exchange rounds: up to kRemcGraphRounds rounds (each a sweep and its
-// exchange step) are captured once as a graph and replayed, the step index x0 + r
+// Many replica-exchange rounds (each a sweep and its exchange step), launched on
+// the stream round after round. With GOAC_REMC_GRAPH, up to kRemcGraphRounds
+// rounds are captured once as a graph and replayed instead, the step index x0 + r
 // read from device memory and advanced by each exchange; the last rounds that do
 // not fill a graph launch the same kernels on the stream. Cells whose MIXED field
-// re-anchors between sweep chunks (workspace sized on the host) run the same
-// rounds without capture.
+// re-anchors between sweep chunks (workspace sized on the host) run without
+// capture.
 extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials,
                                      uint64_t rounds, uint64_t x0, uint64_t seed, uint32_t flags,
                                      int32_t reanchor_every, int32_t* slot) {
     if (!ch) return GOAC_EINVAL;
     goac_ctx* ctx = ch->ctx;
-    if (R < 2 || R > kRemcMaxR || !kT_host || !slot || ch->C % R != 0 || trials == 0 || (flags & ~GOAC_MC_TRACE_HASH))
+    if (R < 2 || R > kRemcMaxR || !kT_host || !slot || ch->C % R != 0 || trials == 0 ||
+        (flags & ~(GOAC_MC_TRACE_HASH | GOAC_REMC_GRAPH)))
         return fail(ctx, GOAC_EINVAL, "remc_run: bad arguments");
     for (int k = 0; k < R; ++k)
         if (!(kT_host[k] > 0.0)) return fail(ctx, GOAC_EINVAL, "remc_run: kT must be positive");
@@ -1664,7 +1666,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     prm.n_blocks = 1;
     prm.block_len = trials;
     prm.reanchor_every = reanchor_every > 0 ? reanchor_every : 1024;
-    prm.flags = flags;
+    prm.flags = flags & GOAC_MC_TRACE_HASH;
     // the ladder is the sweep's table (R rows x 1 block) and the exchange's
     GOAC_TRY(sweep_upload_kT(ch, kT_host, (size_t)R));
     SweepPlan P;
@@ -1673,7 +1675,7 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     ch->max_row = std::max(ch->max_row, R - 1);
     hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, sm, ng, R, slot, ch->sc);
     GOAC_CHECK_LAUNCH(ctx);
-    if (!P.a.inline_anchor) {
+    if (!P.a.inline_anchor || !(flags & GOAC_REMC_GRAPH)) {
         for (uint64_t r = 0; r < rounds; ++r) {
             GOAC_TRY(sweep_enqueue(ch, P, trace, trials, prm.reanchor_every));
             remc_launch(sm, ng, R, ch->kT, x0 + r, nullptr, seed, ch->sc, slot, nullptr, nullptr, nullptr);

@@ -362,13 +362,15 @@ def test_autotune_leaves_chains_unchanged(ctx, cfg2, prec):
     _compare(cell, stats, occ.cpu().numpy(), best.cpu().numpy(), st, prec, V)
 
 
+@pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("prec,groups", [(0, 16), (1, 16), (1, 1100)])
-def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups):
-    """Rounds replayed from one captured graph equal the same rounds launched one
-    by one (sweep + exchange), bit for bit; checked after several replays, after a
-    second call that captures again, and with eager work and synchronisation
-    between the calls. 4400 chains are more than the resident workgroups, so the
-    sweep's work counter, cleared by each round's exchange, is in use."""
+def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups, graph):
+    """goac_remc_run's rounds, launched on the stream or replayed from one captured
+    graph, equal the same rounds launched one by one (sweep + exchange), bit for
+    bit; checked after several replays, after a second call that captures again,
+    and with eager work and synchronisation between the calls. 4400 chains are more
+    than the resident workgroups, so the sweep's work counter, cleared by each
+    round's exchange, is in use."""
     cell, V = cfg2
     R = 4
     ladder = np.array([0.05, 0.1, 0.2, 0.4])
@@ -381,7 +383,7 @@ def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups):
     b.set_rows(np.tile(np.arange(R), groups))
     x = 0
     for rounds in (3, 1, 11):
-        a.remc_run(R, ladder, 700, rounds, x, 5, sa, trace=True)
+        a.remc_run(R, ladder, 700, rounds, x, 5, sa, trace=True, graph=graph)
         for r in range(rounds):
             b.sweep(700, ladder[:, None], 700, seed=5, trace=True)
             b.remc_exchange(R, ladder, x + r, 5, sb)
