@@ -398,6 +398,42 @@ def test_remc_run_graph_matches_eager_rounds(ctx, cfg2, prec, groups, graph):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_remc_run_on_a_cell_with_host_anchors(ctx, prec, graph):
+    """goac_remc_run on the 8x8x8 cell (M = 2048): the mixed field there re-anchors
+    between sweep chunks (2500 trials = two chunks at reanchor_every = 256), which
+    runs every round from the host even when graph replay is asked for; rounds must
+    equal sweeps and exchanges launched one by one, bit for bit."""
+    cell = S.config3()
+    Vg = ctx.build_ewald(cell["lattice"], cell["pos"])
+    pb = G.Problem(ctx, Vg, cell["sublattice"], cell["species"], cell["charge"])
+    del Vg
+    R, groups = 4, 4
+    ladder = np.array([0.05, 0.1, 0.2, 0.4])
+    occ0 = pb.init_occupations(R * groups, seed=3)
+    a = G.Chains(pb, occ0, prec)
+    b = G.Chains(pb, occ0, prec)
+    sa = torch.tensor(np.tile(np.arange(R, dtype=np.int32), groups), device="cuda")
+    sb = sa.clone()
+    b.set_rows(np.tile(np.arange(R), groups))
+    x = 0
+    for rounds in (2, 3):
+        a.remc_run(R, ladder, 2500, rounds, x, 8, sa, trace=True, reanchor_every=256, graph=graph)
+        for r in range(rounds):
+            b.sweep(2500, ladder[:, None], 2500, seed=8, reanchor_every=256, trace=True)
+            b.remc_exchange(R, ladder, x + r, 8, sb)
+        x += rounds
+        oa, _, st_a = a.export()
+        ob, _, st_b = b.export()
+        assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+        assert torch.equal(oa, ob)
+        for f in ("t", "hash", "accepts", "updates", "E", "best_E", "row"):
+            assert np.array_equal(st_a[f], st_b[f]), f
+    Ef = pb.energies(oa, G.GOAC_FP64).cpu().numpy()
+    assert np.abs(Ef - st_a["E"]).max() / len(cell["pos"]) <= TOL[prec]
+
+
 # ------------------------------------------------------------------ GA
 
 @pytest.mark.parametrize("P,prec,gens", [(203, 1, 21), (64, 0, 5), (128, 0, 17), (96, 1, 18)])
