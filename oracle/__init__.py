@@ -313,7 +313,8 @@ def hybrid_round(V, cell, state, slot, pop, r, R, kT, trials, exchanges, generat
         rows = np.empty(C, np.int32)
         for g in range(G):
             rows[g * R + slot[g]] = np.arange(R)
-        mc_run(V, cell, state, seed=seed, n_trials=trials, kT=kT[:, None], block_len=trials, kT_row=rows)
+        mc_run(V, cell, state, seed=seed, n_trials=trials, kT=kT[:, None], block_len=max(trials, 1),
+               kT_row=rows)
         E = state.field("E")
         for g in range(G):
             slot[g], _ = remc_exchange(kT, E[g * R:(g + 1) * R], slot[g], r * exchanges + e, seed, group=g)

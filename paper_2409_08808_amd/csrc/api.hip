@@ -23,42 +23,15 @@ __global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __r
                                  ChainScalars* __restrict__ sc);
 constexpr int kInlineAnchorMaxMp = 1024;
 
-// All work of a context runs on its one stream, so a released block is reused only
-// by work queued after everything that used it. The cache keeps at most
-// kPoolMaxBytes; beyond that released blocks are freed.
-constexpr size_t kPoolMaxBytes = (size_t)8 << 30;
-
+// Arenas of problems and chain sets come from the context's block cache
+// (lifetime.h): a released block is reused only by work queued after everything
+// that used it, since all work of a context runs on its one stream.
 goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out) {
-    const size_t want = (size_t)round_up((int64_t)*bytes, (int64_t)1 << 16);
-    auto it = ctx->pool.lower_bound(want);
-    if (it != ctx->pool.end() && it->first <= 2 * want) {
-        *out = it->second;
-        *bytes = it->first;
-        ctx->pool_bytes -= it->first;
-        ctx->pool.erase(it);
-        return GOAC_OK;
-    }
-    if (hipMalloc(out, want) != hipSuccess) {
-        // release the cache and try once more
-        (void)hipStreamSynchronize(ctx->stream);
-        for (auto& b : ctx->pool) (void)hipFree(b.second);
-        ctx->pool.clear();
-        ctx->pool_bytes = 0;
-        if (hipMalloc(out, want) != hipSuccess) return fail(ctx, GOAC_ENOMEM, "device allocation failed");
-    }
-    *bytes = want;
+    if (!ctx->pool.get(ctx->dev, bytes, out)) return fail(ctx, GOAC_ENOMEM, "device allocation failed");
     return GOAC_OK;
 }
 
-void pool_put(goac_ctx* ctx, void* p, size_t bytes) {
-    if (!p) return;
-    if (ctx->pool_bytes + bytes > kPoolMaxBytes) {
-        (void)hipFree(p);
-        return;
-    }
-    ctx->pool.emplace(bytes, p);
-    ctx->pool_bytes += bytes;
-}
+void pool_put(goac_ctx* ctx, void* p, size_t bytes) { ctx->pool.put(ctx->dev, p, bytes); }
 
 // A copy from pinned memory is queued at once; one from pageable memory makes the
 // host wait. The ring's halves take turns: a half is written again only once the
@@ -585,6 +558,7 @@ extern "C" goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** 
     goac_ctx* ctx = new goac_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->dev.stream = ctx->stream;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
     *out = ctx;
@@ -592,12 +566,12 @@ extern "C" goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** 
 }
 
 // The context is freed once the caller has released it and no problem or chain
-// set made on it is left, in whichever order the two happen.
+// set made on it is left, in whichever order the two happen (lifetime.h).
 static void ctx_free(goac_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int q = 0; q < kWsSlots; ++q)
         if (ctx->ws[q]) (void)hipFree(ctx->ws[q]);
-    for (auto& b : ctx->pool) (void)hipFree(b.second);
+    ctx->pool.clear(ctx->dev);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     for (int h = 0; h < 2; ++h)
         if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
@@ -605,15 +579,7 @@ static void ctx_free(goac_ctx* ctx) {
     delete ctx;
 }
 
-static void ctx_release_dep(goac_ctx* ctx) {
-    if (--ctx->live == 0 && ctx->released) ctx_free(ctx);
-}
-
-extern "C" void goac_ctx_destroy(goac_ctx* ctx) {
-    if (!ctx || ctx->released) return;
-    ctx->released = true;
-    if (ctx->live == 0) ctx_free(ctx);
-}
+extern "C" void goac_ctx_destroy(goac_ctx* ctx) { release_context(ctx, ctx_free); }
 
 extern "C" const char* goac_last_error(const goac_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -820,7 +786,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     }
     // ht beyond M is zero
     if (Mp > M && hipMemsetAsync(d.ht + M, 0, (Mp - M) * 8, sm) != hipSuccess) return bail(GOAC_EHIP);
-    ++ctx->live;
+    ctx->holders.attach();
     *out = pb;
     return GOAC_OK;
 }
@@ -829,10 +795,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
 // cache, whose blocks only work queued later on the same stream reuses.
 extern "C" void goac_problem_destroy(goac_problem* pb) {
     if (!pb) return;
-    goac_ctx* ctx = pb->ctx;
-    problem_free(pb);
-    delete pb;
-    ctx_release_dep(ctx);
+    destroy_dependent(pb->ctx, pb, problem_free, ctx_free);
 }
 
 extern "C" goac_status goac_problem_get_info(const goac_problem* pb, goac_problem_info* out) {
@@ -1276,7 +1239,7 @@ extern "C" goac_status goac_chains_create(goac_problem* pb, int64_t C, const uin
         delete ch;
         return st;
     }
-    ++ctx->live;
+    ctx->holders.attach();
     *out = ch;
     return GOAC_OK;
 }
@@ -1321,17 +1284,14 @@ extern "C" goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_
         delete ch;
         return st;
     }
-    ++ctx->live;
+    ctx->holders.attach();
     *out = ch;
     return GOAC_OK;
 }
 
 extern "C" void goac_chains_destroy(goac_chains* ch) {
     if (!ch) return;
-    goac_ctx* ctx = ch->ctx;
-    chains_free(ch);
-    delete ch;
-    ctx_release_dep(ctx);
+    destroy_dependent(ch->ctx, ch, chains_free, ctx_free);
 }
 
 extern "C" goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows) {

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/goac.h"
+#include "lifetime.h"
 
 namespace goac {
 
@@ -163,6 +164,18 @@ struct McInst {
 }  // namespace goac
 
 // ------------------------------------------------------------------ host objects
+namespace goac {
+// Device interface of the context's block cache and lifetime (lifetime.h): HIP
+// memory whose users are ordered by the context's stream.
+struct HipDev {
+    hipStream_t stream = nullptr;
+    bool alloc(void** p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
+    void release(void* p) { (void)hipFree(p); }
+    void drain() { (void)hipStreamSynchronize(stream); }
+};
+constexpr size_t kPoolMaxBytes = (size_t)8 << 30;  // released blocks a context keeps
+}  // namespace goac
+
 constexpr int kWsSlots = 3;   // scratch slots: 0 kernels' operands, 1 GEMM partials, 2 selection
 // host-side tables of the last Ewald build and the inputs they were made from
 struct EwaldPlan {
@@ -184,8 +197,8 @@ struct goac_ctx {
     std::string err;
     void* ws[kWsSlots] = {nullptr, nullptr, nullptr};  // scratch, grown on demand
     size_t ws_size[kWsSlots] = {0, 0, 0};
-    std::multimap<size_t, void*> pool;  // released arenas by size, reused by later ones
-    size_t pool_bytes = 0;
+    goac::HipDev dev;                   // the stream-ordered device of the block cache
+    goac::BlockCache<goac::HipDev> pool{goac::kPoolMaxBytes};  // released arenas, reused by later ones
     // pinned staging of host-to-device copies: two halves, each with the event
     // recorded after the copies last queued from it
     char* stage = nullptr;
@@ -196,8 +209,7 @@ struct goac_ctx {
     bool capturing = false;  // a stream capture is open on the context's work
     hipStream_t cap = nullptr;  // private stream that graph captures record on (created on first use)
     EwaldPlan ewald;            // reused by a build of the same cell and parameters
-    int64_t live = 0;           // problems and chain sets not yet destroyed
-    bool released = false;      // goac_ctx_destroy has been called
+    goac::Holders holders;      // the caller's handle and the live problems and chain sets
 };
 
 struct goac_problem {
