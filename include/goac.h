@@ -13,7 +13,11 @@
  *     context, problems, chain sets and their internal device memory.
  *   - Asynchrony: device work is queued on the context's stream; outputs are
  *     valid once that stream has synchronised. Argument, shape and composition
- *     errors are found before anything is queued and returned synchronously.
+ *     errors are returned synchronously, and a rejected call changes no output.
+ *     Occupations the caller passes are checked on the device (every mobile
+ *     species id below n_species, the species counts of every sublattice equal
+ *     to the problem's: the occupancy constraints of Eq. 2); the host waits for
+ *     that check, which runs before any kernel that reads the rows.
  *     A device fault surfaces as GOAC_EHIP on a later call.
  *   - Errors: every call returns a goac_status; goac_last_error() describes the
  *     last failure on a context. Nothing is thrown across the ABI.
@@ -37,8 +41,9 @@ typedef enum {
     GOAC_EHIP = -3,        /* HIP runtime error or an earlier device fault       */
     GOAC_ENOTNEUTRAL = -4, /* the cell's total charge is not zero                */
     GOAC_EINEXACT = -5,    /* a shifted charge is not exact in bfloat16          */
-    GOAC_EDRIFT = -6,      /* the FP32 field left its error budget (see mc_sweep) */
-    GOAC_ESTATE = -7       /* object used with the wrong context or precision    */
+    GOAC_EDRIFT = -6,      /* a chain's FP32 field left its error bound (chains_export) */
+    GOAC_ESTATE = -7       /* objects of different contexts, or a chain set of
+                              several problems where one is required            */
 } goac_status;
 
 /* Arithmetic of energies and of the Monte Carlo field.
@@ -153,9 +158,13 @@ goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64_t seed, ui
  *   GOAC_MIXED : q = c + dq with the exact integer shift c; Phi = dQ V_hi + dQ
  *                V_lo on bfloat16 matrix cores with FP32 accumulation, then
  *                E_p = E~ + sum_k dq_k (h~_k + Phi_k / 2) in FP64.
- *   occ_dev : P x n uint8;  E_dev : P FP64 output.
- * Errors: EINVAL; EINEXACT for GOAC_MIXED when a shifted charge is not exact
- * in bfloat16. */
+ *   occ_dev : P x n uint8 (P <= 2^30);  E_dev : P FP64 output.
+ * The rows are checked first (conventions above). The energy kernels are queued
+ * right behind the check and skip all work when it fails, so the call waits for
+ * the check alone and the device runs on without a gap.
+ * Errors: EINVAL (arguments; a row breaking the composition, E_dev then
+ * unchanged); EINEXACT for GOAC_MIXED when a shifted charge is not exact in
+ * bfloat16. */
 goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
                           goac_precision prec, double* E_dev);
 
@@ -171,12 +180,14 @@ goac_status goac_energies_tile(goac_problem* pb, int64_t P, int32_t kt);
  * keeps the fastest for later calls with P rows, as goac_energies_tile would.
  *   kt_out : the chosen tile (may be NULL)
  * Synchronises; takes P doubles of scratch from the context's cache for the call.
- * Errors: EINVAL; EINEXACT as goac_energies. */
+ * Errors: EINVAL (arguments, rows as goac_energies); EINEXACT as goac_energies. */
 goac_status goac_energies_autotune(goac_problem* pb, int64_t P, const uint8_t* occ_dev, int32_t* kt_out);
 
 /* The k lowest configurations among P candidates (Methodology: the n lowest
  * structures are the output): FP64 energies ordered by (E, index).
- *   idx_dev : k int64 output; E_dev : k FP64 output (k <= P). */
+ *   idx_dev : k int64 output; E_dev : k FP64 output (k <= P).
+ * Errors: EINVAL (arguments; a row breaking the composition, checked first with
+ * a wait). */
 goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t* occ_dev, int32_t k,
                            int64_t* idx_dev, double* E_dev);
 
@@ -200,8 +211,9 @@ void goac_chains_destroy(goac_chains* ch);
 /* Many independent problems in one set of chains: instance i has
  * chains_per_instance[i] chains; chain ids restart at 0 for every instance and
  * the instance id is i. occ_dev holds the start occupations of all chains,
- * instance after instance, each row n_i long. Problems must share the context.
- * The sweep runs every chain of every instance in one persistent launch. */
+ * instance after instance, each row n_i long. Problems must share the context
+ * (GOAC_ESTATE otherwise). The sweep runs every chain of every instance in one
+ * persistent launch. */
 goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_t n_instances,
                                      const int64_t* chains_per_instance, const uint8_t* occ_dev,
                                      goac_precision prec, goac_chains** out);
@@ -240,8 +252,9 @@ goac_status goac_chains_set_rows(goac_chains* ch, const int32_t* rows_host);
  * GOAC_MIXED decides from the FP32 field only when the FP64 decision cannot
  * differ within a rigorous error bound; otherwise it recomputes phi_i and phi_j
  * in FP64. The field is re-anchored in FP64 between chunks once a chain has made
- * reanchor_every field updates. Returns GOAC_EDRIFT if the field left its
- * bound (a NaN or an overflow). */
+ * reanchor_every field updates. A chain whose FP32 error bound breaks (a NaN or
+ * an overflow) keeps deciding every trial by the exact FP64 rule and sets its
+ * status; goac_chains_export then reports GOAC_EDRIFT. */
 goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* params);
 
 typedef struct {
@@ -270,7 +283,10 @@ goac_status goac_chains_autotune(goac_chains* ch, uint64_t probe_trials, double 
                                  int32_t* per_cu_out);
 
 /* Copy chain results to caller buffers (any pointer may be NULL):
- *   occ_dev, best_occ_dev : C x n; stats_dev : C goac_chain_stats (device). */
+ *   occ_dev, best_occ_dev : C x n; stats_dev : C goac_chain_stats (device).
+ * Synchronises: after the copies the chains' status flags are read, and the call
+ * returns GOAC_EDRIFT (the copies made) when any chain's FP32 field has left its
+ * error bound (a chain's flag stays set until goac_chains_load rebuilds it). */
 goac_status goac_chains_export(goac_chains* ch, uint8_t* occ_dev, uint8_t* best_occ_dev,
                                goac_chain_stats* stats_dev);
 
@@ -304,7 +320,10 @@ goac_status goac_remc_exchange(goac_chains* ch, int32_t R, const double* kT_host
  * (more than 1024 mobile positions) always run without capture.
  *   flags : GOAC_MC_TRACE_HASH and/or GOAC_REMC_GRAPH;  reanchor_every : as in
  *           goac_mc_params
- *   slot_dev : groups x R int32 (in/out). Synchronises. */
+ *   slot_dev : groups x R int32 (in/out).
+ * Launched round after round, the rounds are queued on the stream and the call
+ * returns without waiting; with GOAC_REMC_GRAPH it waits for the stream before
+ * releasing the graph. */
 goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* kT_host, uint64_t trials, uint64_t rounds,
                           uint64_t x0, uint64_t seed, uint32_t flags, int32_t reanchor_every, int32_t* slot_dev);
 
@@ -328,9 +347,10 @@ typedef struct {
  *               of Philox at counter (position, c, g, 4))
  *   mutation  : with probability p_mut one valid swap (Philox at (c, g, 1, 5))
  *   pop_in_dev : P x n; E_in_dev : P FP64; pop_out_dev : P x n (not aliasing pop_in).
- * Errors: EINVAL, also if (E_max - E_min) 2^30 P exceeds 2^62 (or an energy is
- * not a number): the weights are checked before any child is formed, the host
- * waiting for them, and pop_out_dev is then left untouched. */
+ * Errors: EINVAL for a parent row that breaks the composition, and if (E_max -
+ * E_min) 2^30 P exceeds 2^62 (or an energy is not a number): the rows and then
+ * the weights are checked before any child is formed, the host waiting for
+ * them, and pop_out_dev is then left untouched. */
 goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
@@ -345,8 +365,10 @@ goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_i
  *   pop_dev : P x n (in/out): the population, then the last generation's children
  *   E_dev   : P FP64 (in/out): energies of pop_dev, then of the returned population
  *   precision : GOAC_FP64 or GOAC_MIXED
- * Errors: EINVAL as goac_ga_generation (the roulette range is checked once, after
- * the last generation; pop_dev and E_dev are then unspecified). Synchronises;
+ * Errors: EINVAL as goac_ga_generation (the rows are checked first, with a wait,
+ * and nothing is changed when one breaks the composition; the roulette range is
+ * checked once, after the last generation, and pop_dev and E_dev are then
+ * unspecified). Synchronises;
  * takes a second population buffer from the context's cache for the call. */
 goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop_dev, double* E_dev,
                         const goac_ga_params* params, int32_t generations, int32_t precision);
@@ -395,10 +417,11 @@ typedef struct {
  *              rows are set from it at the start
  *   pop_dev  : P x n population (in/out); E_dev : P FP64, the energies of the
  *              returned population (out)
- * Synchronises twice: once after the GA phase (a roulette failure in any of its
- * generations is reported then, GOAC_EINVAL) and once for the composition check
- * of the reload. The chain set owns the scratch memory of the round (grown on
- * demand, freed with the chains). */
+ * Synchronises three times: for the composition check of pop_dev at the start
+ * (EINVAL, nothing changed), after the GA phase (a roulette failure in any of its
+ * generations is reported then, GOAC_EINVAL) and for the composition check of
+ * the reload. ESTATE for a chain set of several problems. The chain set owns the
+ * scratch memory of the round (grown on demand, freed with the chains). */
 goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int64_t P, uint8_t* pop_dev, double* E_dev,
                               const goac_hybrid_params* params);
 
@@ -413,8 +436,8 @@ goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int64_t P, uin
  * rounding noise, so the window makes the choice well defined); it stops when the
  * lowest dE is >= -tol or after max_steps swaps.
  *   occ_dev   : P x n uint8, read and overwritten with the local minima (fixed
- *               sites are left as they are; ids >= n_species are read as the last
- *               species, as in goac_energies)
+ *               sites are left as they are); checked first as in goac_energies
+ *               (EINVAL, nothing changed)
  *   max_steps : swaps per configuration at most; tol >= 0 (eV), e.g. 1e-9
  *   steps_dev : P int64 output (swaps taken) or NULL
  *   E_dev     : P FP64 output (energy of the result) or NULL

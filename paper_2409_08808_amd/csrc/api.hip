@@ -507,6 +507,49 @@ __global__ void k_zero_i32(int32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// *flag |= 1 when a chain's FP32 field has left its error bound
+__global__ void k_drift_flag(int64_t C, const ChainScalars* __restrict__ sc, int32_t* __restrict__ flag) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C && sc[c].status) atomicOr(flag, 1);
+}
+
+// the verdict word, its pinned host copy and the event after the copy
+static goac_status check_buffers(goac_ctx* ctx) {
+    if (!ctx->chk_dev) GOAC_HIP(ctx, hipMalloc((void**)&ctx->chk_dev, 256));
+    if (!ctx->chk_host) GOAC_HIP(ctx, hipHostMalloc((void**)&ctx->chk_host, 256, hipHostMallocDefault));
+    if (!ctx->chk_ev) GOAC_HIP(ctx, hipEventCreateWithFlags(&ctx->chk_ev, hipEventDisableTiming));
+    return GOAC_OK;
+}
+
+// queue the copy of the verdict to the host and the event after it
+static goac_status check_publish(goac_ctx* ctx) {
+    GOAC_HIP(ctx, hipMemcpyAsync(ctx->chk_host, ctx->chk_dev, 4, hipMemcpyDeviceToHost, ctx->stream));
+    GOAC_HIP(ctx, hipEventRecord(ctx->chk_ev, ctx->stream));
+    return GOAC_OK;
+}
+
+goac_status rows_check_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ) {
+    goac_ctx* ctx = pb->ctx;
+    if (ctx->capturing) return fail(ctx, GOAC_EINVAL, "row check inside a stream capture");
+    if (P < 0 || P > ((int64_t)1 << 30) || (P > 0 && !occ)) return fail(ctx, GOAC_EINVAL, "row check: bad rows");
+    GOAC_TRY(check_buffers(ctx));
+    const ProblemDev& d = pb->d;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ctx->chk_dev, 1);
+    if (P > 0)
+        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)P), dim3(256), 0, ctx->stream, d.n, d.M, d.S, d.E, d.tab,
+                           d.mob, d.msub, occ, ctx->chk_dev);
+    GOAC_CHECK_LAUNCH(ctx);
+    return check_publish(ctx);
+}
+
+goac_status rows_check_wait(goac_ctx* ctx, const char* who) {
+    GOAC_HIP(ctx, hipEventSynchronize(ctx->chk_ev));
+    if (*ctx->chk_host)
+        return fail(ctx, GOAC_EINVAL,
+                    std::string(who) + ": an occupation holds an unknown species or breaks the problem's composition");
+    return GOAC_OK;
+}
+
 }  // namespace goac
 
 using namespace goac;
@@ -575,6 +618,9 @@ static void ctx_free(goac_ctx* ctx) {
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     for (int h = 0; h < 2; ++h)
         if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
+    if (ctx->chk_dev) (void)hipFree(ctx->chk_dev);
+    if (ctx->chk_host) (void)hipHostFree(ctx->chk_host);
+    if (ctx->chk_ev) (void)hipEventDestroy(ctx->chk_ev);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
@@ -846,15 +892,20 @@ extern "C" goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t*
                                      double* E) {
     if (!pb) return GOAC_EINVAL;
     goac_ctx* ctx = pb->ctx;
-    if (P < 0 || (P > 0 && (!occ || !E))) return fail(ctx, GOAC_EINVAL, "energies: bad arguments");
+    if (P < 0 || P > ((int64_t)1 << 30) || (P > 0 && (!occ || !E)))
+        return fail(ctx, GOAC_EINVAL, "energies: bad arguments");
+    if (prec != GOAC_FP64 && prec != GOAC_MIXED) return fail(ctx, GOAC_EINVAL, "energies: unknown precision");
+    if (prec == GOAC_MIXED && !pb->d.mixed_exact)
+        return fail(ctx, GOAC_EINEXACT, "energies: a shifted charge is not bf16-exact");
     if (P == 0) return GOAC_OK;
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    if (prec == GOAC_MIXED) {
-        if (!pb->d.mixed_exact) return fail(ctx, GOAC_EINEXACT, "energies: a shifted charge is not bf16-exact");
-        return energies_mixed(pb, P, occ, E);
-    }
-    if (prec != GOAC_FP64) return fail(ctx, GOAC_EINVAL, "energies: unknown precision");
-    return energies_fp64(pb, P, occ, E);
+    // The rows are checked first. The energy kernels are queued right behind the
+    // check and skip their work when it failed, so the host waits for the check
+    // alone while the device goes on without a gap; a rejected call leaves E as it was.
+    GOAC_TRY(rows_check_enqueue(pb, P, occ));
+    GOAC_TRY(prec == GOAC_MIXED ? energies_mixed(pb, P, occ, E, 0, ctx->chk_dev)
+                                : energies_fp64(pb, P, occ, E, ctx->chk_dev));
+    return rows_check_wait(ctx, "energies");
 }
 
 // tiles of the mixed population product: 1, 2, 4 or 8 n-tiles of 128 positions per
@@ -885,6 +936,7 @@ extern "C" goac_status goac_energies_autotune(goac_problem* pb, int64_t P, const
     if (P <= 0 || !occ) return fail(ctx, GOAC_EINVAL, "energies_autotune: bad arguments");
     if (!pb->d.mixed_exact) return fail(ctx, GOAC_EINEXACT, "energies_autotune: a shifted charge is not bf16-exact");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(rows_check(pb, P, occ, "energies_autotune"));
     size_t bytes = (size_t)P * 8;
     void* buf = nullptr;
     GOAC_TRY(pool_get(ctx, &bytes, &buf));
@@ -930,6 +982,7 @@ extern "C" goac_status goac_topk_fp64(goac_problem* pb, int64_t P, const uint8_t
     goac_ctx* ctx = pb->ctx;
     if (P <= 0 || k <= 0 || k > P || !occ || !idx || !Eout) return fail(ctx, GOAC_EINVAL, "topk: bad arguments");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(rows_check(pb, P, occ, "topk"));
     const size_t bE = round_up(P * 8, 256), bC = round_up(P * 4, 256);
     void* sel = nullptr;
     GOAC_TRY(workspace(ctx, 2, bE + bC, &sel));
@@ -987,6 +1040,10 @@ goac_status ga_check_err(goac_ctx* ctx, const int32_t* err) {
 extern "C" goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
                                           const goac_ga_params* prm, uint8_t* pop_out) {
     if (!pb) return GOAC_EINVAL;
+    goac_ctx* ctx = pb->ctx;
+    if (P <= 0 || !pop_in) return fail(ctx, GOAC_EINVAL, "ga_generation: bad arguments");
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(rows_check(pb, P, pop_in, "ga_generation"));
     int32_t* err = nullptr;
     return ga_generation_enqueue(pb, P, pop_in, E_in, prm, pop_out, true, &err, nullptr, true);
 }
@@ -1011,6 +1068,8 @@ extern "C" goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop, do
         return fail(ctx, GOAC_EINVAL, "ga_run: bad arguments");
     if (generations == 0) return GOAC_OK;
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    // the caller's population is checked once; its children keep the composition
+    GOAC_TRY(rows_check(pb, P, pop, "ga_run"));
     hipStream_t sm = ctx->stream;
     if (!ctx->cap) GOAC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
     // the second population and the generation counter
@@ -1027,7 +1086,7 @@ extern "C" goac_status goac_ga_run(goac_problem* pb, int64_t P, uint8_t* pop, do
         goac_ga_params gp = *prm;
         gp.generation = g;
         GOAC_TRY(ga_generation_enqueue(pb, P, bufs[k & 1], E, &gp, bufs[(k + 1) & 1], k == 0, &err, gd));
-        return goac_energies(pb, P, bufs[(k + 1) & 1], pr, E);
+        return energies_enqueue(pb, P, bufs[(k + 1) & 1], pr, E);
     };
     goac_status st = gen(0, nullptr, prm->generation);
     int32_t k = 1;
@@ -1255,9 +1314,13 @@ extern "C" goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_
     ch->prec = prec;
     int64_t C = 0, rowoff = 0;
     for (int i = 0; i < n_inst; ++i) {
-        if (!pbs[i] || pbs[i]->ctx != ctx || cpi[i] < 0) {
+        if (!pbs[i] || cpi[i] < 0) {
             delete ch;
             return fail(ctx, GOAC_EINVAL, "chains_create_batch: bad instance");
+        }
+        if (pbs[i]->ctx != ctx) {
+            delete ch;
+            return fail(ctx, GOAC_ESTATE, "chains_create_batch: problems of different contexts");
         }
         ch->pbs.push_back(pbs[i]);
         ch->inst_id.push_back((uint32_t)i);
@@ -1528,10 +1591,9 @@ extern "C" goac_status goac_chains_autotune(goac_chains* ch, uint64_t probe_tria
     return GOAC_OK;
 }
 
-extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats) {
-    if (!ch) return GOAC_EINVAL;
+namespace goac {
+goac_status chains_export_enqueue(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats) {
     goac_ctx* ctx = ch->ctx;
-    GOAC_HIP(ctx, hipSetDevice(ctx->device));
     for (size_t i = 0; i < ch->pbs.size(); ++i) {
         goac_problem* pb = ch->pbs[i];
         const ProblemDev& d = pb->d;
@@ -1546,6 +1608,27 @@ extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t
                            pb->n_fixed, d.ref_occ, first, ch->sc, ch->occ, ch->best, o, b, stats);
         GOAC_CHECK_LAUNCH(ctx);
     }
+    return GOAC_OK;
+}
+}  // namespace goac
+
+// The copies, then the chains' drift flags; the host waits for the flags (and so
+// for the copies, which precede them on the stream).
+extern "C" goac_status goac_chains_export(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    if (ctx->capturing) return fail(ctx, GOAC_EINVAL, "chains_export inside a stream capture");
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(chains_export_enqueue(ch, occ, best, stats));
+    GOAC_TRY(check_buffers(ctx));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ctx->chk_dev, 1);
+    hipLaunchKernelGGL(k_drift_flag, dim3((unsigned)((ch->C + 255) / 256)), dim3(256), 0, ctx->stream, ch->C, ch->sc,
+                       ctx->chk_dev);
+    GOAC_CHECK_LAUNCH(ctx);
+    GOAC_TRY(check_publish(ctx));
+    GOAC_HIP(ctx, hipEventSynchronize(ctx->chk_ev));
+    if (*ctx->chk_host)
+        return fail(ctx, GOAC_EDRIFT, "chains_export: a chain's FP32 field left its error bound");
     return GOAC_OK;
 }
 
@@ -1633,7 +1716,8 @@ extern "C" goac_status goac_remc_run(goac_chains* ch, int32_t R, const double* k
     GOAC_TRY(sweep_plan(ch, &prm, ch->tuned_wg, ch->tuned_per_cu, &P));
     const bool trace = (flags & GOAC_MC_TRACE_HASH) != 0;
     ch->max_row = std::max(ch->max_row, R - 1);
-    hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, sm, ng, R, slot, ch->sc);
+    hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)ng), dim3(R <= 128 ? 64 : 256), (size_t)((R + 31) / 32) * 4, sm,
+                       ng, R, slot, ch->sc);
     GOAC_CHECK_LAUNCH(ctx);
     if (!P.a.inline_anchor || !(flags & GOAC_REMC_GRAPH)) {
         for (uint64_t r = 0; r < rounds; ++r) {

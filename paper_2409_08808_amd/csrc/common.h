@@ -210,6 +210,12 @@ struct goac_ctx {
     hipStream_t cap = nullptr;  // private stream that graph captures record on (created on first use)
     EwaldPlan ewald;            // reused by a build of the same cell and parameters
     goac::Holders holders;      // the caller's handle and the live problems and chain sets
+    // verdict of the last check of caller rows (composition, species ids) or of the
+    // chains' drift flags: a device word that kernels queued after the check read,
+    // its pinned host copy and the event recorded after that copy
+    int32_t* chk_dev = nullptr;
+    int32_t* chk_host = nullptr;
+    hipEvent_t chk_ev = nullptr;
 };
 
 struct goac_problem {
@@ -323,7 +329,7 @@ struct McArgs {
 
 goac_status mc_launch(goac_ctx* ctx, const McArgs& a, bool mixed, bool trace, int wg, size_t lds, int grid);
 goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
-                      const int32_t* mob, const double* charge, double* Q);
+                      const int32_t* mob, const double* charge, double* Q, const int32_t* gate = nullptr);
 
 // scratch memory of a context (grown, never shrunk)
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
@@ -335,10 +341,31 @@ goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out);
 goac_status upload(goac_ctx* ctx, void* dst, const void* src, size_t bytes);
 void pool_put(goac_ctx* ctx, void* p, size_t bytes);
 
+// Occupancy constraints of Eq. 2 on P caller rows (P x n): every mobile species id
+// below the problem's species count and the species counts of every sublattice
+// equal to the problem's. rows_check_enqueue queues the check and leaves its verdict
+// in ctx->chk_dev (non-zero: a row breaks them), which kernels queued afterwards
+// may read; rows_check_wait waits for that check alone and returns EINVAL on a
+// broken row.
+goac_status rows_check_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ);
+goac_status rows_check_wait(goac_ctx* ctx, const char* who);
+inline goac_status rows_check(goac_problem* pb, int64_t P, const uint8_t* occ, const char* who) {
+    GOAC_TRY(rows_check_enqueue(pb, P, occ));
+    return rows_check_wait(pb->ctx, who);
+}
+
 // population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies
-// by (E, index); cnt_scratch holds P int32
-goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt = 0);
-goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E);
+// by (E, index); cnt_scratch holds P int32. With a gate, the kernels that read the
+// rows and write E do nothing while *gate is non-zero (rows a check rejected).
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt = 0,
+                           const int32_t* gate = nullptr);
+goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E,
+                          const int32_t* gate = nullptr);
+// copies of the chains' occupations, best occupations and counters (any may be
+// null), queued on the stream without a wait
+goac_status chains_export_enqueue(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats);
+// energies in either precision, without a check of the rows (rows the library made)
+goac_status energies_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ, goac_precision prec, double* E);
 goac_status ga_generation_enqueue(goac_problem* pb, int64_t P, const uint8_t* pop_in, const double* E_in,
                                   const goac_ga_params* prm, uint8_t* pop_out, bool zero_err, int32_t** err_out,
                                   const uint32_t* g_dev = nullptr, bool check_first = false);

@@ -172,6 +172,7 @@ extern "C" goac_status goac_gd_run(goac_problem* pb, int64_t P, uint8_t* occ_dev
     const size_t lds = (size_t)d.Mp * (2 * sizeof(double) + 2);
     if (lds > 160 * 1024 - 1024) return fail(ctx, GOAC_EINVAL, "gd_run: too many mobile positions for one workgroup");
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(rows_check(pb, P, occ_dev, "gd_run"));
     if (lds > 64 * 1024)
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_gd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_gd, dim3((unsigned)P), dim3(kGdThreads), lds, ctx->stream, d.n, d.M, d.Mp, d.E, d.mob,

@@ -347,10 +347,10 @@ __global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int3
                                                       const __hip_bfloat16* __restrict__ dQ,
                                                       const double* __restrict__ ht, const double* __restrict__ part,
                                                       const double* __restrict__ lin, const double* __restrict__ Ed,
-                                                      double* __restrict__ E) {
+                                                      double* __restrict__ E, const int32_t* __restrict__ gate) {
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (p >= P) return;
+    if (p >= P || (gate && *gate)) return;
     double s = 0.0;
     if (!lin)
         for (int k = lane; k < M; k += 64) s += (double)__bfloat162float(dQ[p * Mp + k]) * ht[k];
@@ -364,10 +364,11 @@ __global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int3
 // 8 consecutive k per thread written as one 16-byte store
 __global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
                            const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
-                           const double* __restrict__ dq, __hip_bfloat16* __restrict__ out) {
+                           const double* __restrict__ dq, __hip_bfloat16* __restrict__ out,
+                           const int32_t* __restrict__ gate) {
     const int64_t p = blockIdx.y;
     const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8;
-    if (k0 >= Mp) return;
+    if (k0 >= Mp || (gate && *gate)) return;
     __hip_bfloat16 v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -375,7 +376,7 @@ __global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t 
         float x = 0.0f;
         if (k < M) {
             const int e = occ[p * n + mob[k]];
-            x = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+            x = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // ids are checked; the clamp keeps reads in bounds
         }
         v[q] = __float2bfloat16(x);
     }
@@ -397,9 +398,11 @@ __global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, i
                                                          const double* __restrict__ dq,
                                                          const double* __restrict__ ht,
                                                          __hip_bfloat16* __restrict__ out,
-                                                         double* __restrict__ lin) {
+                                                         double* __restrict__ lin,
+                                                         const int32_t* __restrict__ gate) {
     extern __shared__ __align__(16) uint8_t rows[];
     __shared__ double wsum[R][4];
+    if (gate && *gate) return;
     const int64_t p0 = (int64_t)blockIdx.x * R;
     const int64_t ld = round_up(n, 16);
 #pragma unroll
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, i
                 double x = 0.0;
                 if (k < M) {
                     const int e = row[site[q]];
-                    x = dq[sub[q] * E + (e < E ? e : E - 1)];   // out-of-range ids read the last species
+                    x = dq[sub[q] * E + (e < E ? e : E - 1)];   // ids are checked; the clamp keeps reads in bounds
                     acc[r] += x * h[q];
                 }
                 v[q] = __float2bfloat16((float)x);
@@ -470,9 +473,9 @@ __global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, i
 // Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
 __global__ void k_build_q64(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
                             const int32_t* __restrict__ mob, const double* __restrict__ charge,
-                            double* __restrict__ out) {
+                            double* __restrict__ out, const int32_t* __restrict__ gate) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= P * (int64_t)Mp) return;
+    if (idx >= P * (int64_t)Mp || (gate && *gate)) return;
     const int64_t p = idx / Mp;
     const int k = (int)(idx - p * Mp);
     double v = 0.0;
@@ -489,10 +492,10 @@ __global__ __launch_bounds__(256) void k_pop_fp64_finalize(int64_t P, int32_t M,
                                                            const double* __restrict__ Q,
                                                            const double* __restrict__ Phi,
                                                            const double* __restrict__ h, const double* __restrict__ Ed,
-                                                           double* __restrict__ E) {
+                                                           double* __restrict__ E, const int32_t* __restrict__ gate) {
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (p >= P) return;
+    if (p >= P || (gate && *gate)) return;
     double s = 0.0;
     for (int k = lane; k < M; k += 64) s += Q[p * Mp + k] * (h[k] + 0.5 * Phi[p * Mp + k]);
 #pragma unroll
@@ -501,15 +504,16 @@ __global__ __launch_bounds__(256) void k_pop_fp64_finalize(int64_t P, int32_t M,
 }
 
 goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* occ,
-                      const int32_t* mob, const double* charge, double* Q) {
+                      const int32_t* mob, const double* charge, double* Q, const int32_t* gate) {
     const int64_t tot = P * (int64_t)Mp;
     hipLaunchKernelGGL(k_build_q64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, P, n, M, Mp, E,
-                       occ, mob, charge, Q);
+                       occ, mob, charge, Q, gate);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
 
-goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req) {
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req,
+                           const int32_t* gate) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
@@ -564,27 +568,27 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
         const unsigned g = (unsigned)((P + R - 1) / R);
         if (R == 4)
             hipLaunchKernelGGL(k_build_dq_staged<4>, dim3(g), dim3(256), 4 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
         else if (R == 2)
             hipLaunchKernelGGL(k_build_dq_staged<2>, dim3(g), dim3(256), 2 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
         else
             hipLaunchKernelGGL(k_build_dq_staged<1>, dim3(g), dim3(256), ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin);
+                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
     } else
         hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream,
-                           P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ);
+                           P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ, gate);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)total), dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo,
                        part, (int32_t)MT, KT);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
-                       n_parts, dQ, d.ht, part, lin, d.Ed, E);
+                       n_parts, dQ, d.ht, part, lin, d.Ed, E, gate);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
 
-goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E) {
+goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, const int32_t* gate) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const size_t qb = round_up((size_t)P * d.Mp * sizeof(double), 256);
@@ -593,13 +597,19 @@ goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, doubl
     if (st != GOAC_OK) return st;
     double* Q = (double*)ws;
     double* Phi = (double*)((char*)ws + qb);
-    GOAC_TRY(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q));
+    GOAC_TRY(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q, gate));
     st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr);
     if (st != GOAC_OK) return st;
     hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M,
-                       d.Mp, Q, Phi, d.h, d.Ed, E);
+                       d.Mp, Q, Phi, d.h, d.Ed, E, gate);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
 
+}  // namespace goac
+
+namespace goac {
+goac_status energies_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ, goac_precision prec, double* E) {
+    return prec == GOAC_MIXED ? energies_mixed(pb, P, occ, E) : energies_fp64(pb, P, occ, E);
+}
 }  // namespace goac

@@ -18,18 +18,31 @@
 
 namespace goac {
 
-// rows of every group from its slot permutation (a non-permutation is left alone)
+// rows of every group from its slot permutation: one workgroup per group checks
+// that the slots are a permutation of 0..R-1 (an LDS bit per value, as the
+// exchange step does) and leaves a group that is not one unchanged
 __global__ void k_rows_from_slot(int64_t n_groups, int32_t R, const int32_t* __restrict__ slot,
                                  ChainScalars* __restrict__ sc) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ uint32_t seen[];
+    __shared__ int s_bad;
+    const int64_t g = blockIdx.x;
     if (g >= n_groups) return;
     const int32_t* sl = slot + g * R;
-    uint64_t seen = 0;
-    for (int k = 0; k < R; ++k) {
-        if ((uint32_t)sl[k] >= (uint32_t)R || (R <= 64 && ((seen >> sl[k]) & 1))) return;
-        if (R <= 64) seen |= 1ull << sl[k];
+    for (int w = threadIdx.x; w < (R + 31) / 32; w += blockDim.x) seen[w] = 0;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < R; k += blockDim.x) {
+        const int32_t v = sl[k];
+        if ((uint32_t)v >= (uint32_t)R) {
+            s_bad = 1;
+        } else {
+            const uint32_t bit = 1u << (v & 31);
+            if (atomicOr(&seen[v >> 5], bit) & bit) s_bad = 1;
+        }
     }
-    for (int k = 0; k < R; ++k) sc[g * R + sl[k]].row = k;
+    __syncthreads();
+    if (s_bad) return;
+    for (int k = threadIdx.x; k < R; k += blockDim.x) sc[g * R + sl[k]].row = k;
 }
 
 // dst row r = src row idx[r]
@@ -82,9 +95,9 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     goac_ctx* ctx = ch->ctx;
     if (!prm || !slot_dev || !pop_dev || !E_dev || P <= 0 || P > (1 << 30))
         return fail(ctx, GOAC_EINVAL, "hybrid_round: bad arguments");
-    if (ch->pbs.size() != 1) return fail(ctx, GOAC_EINVAL, "hybrid_round: chains of one problem only");
+    if (ch->pbs.size() != 1) return fail(ctx, GOAC_ESTATE, "hybrid_round: chains of one problem only");
     const int32_t R = prm->R;
-    if (R < 2 || ch->C % R != 0 || !prm->kT_host || prm->exchanges < 0 || prm->generations < 0 ||
+    if (R < 2 || R > (1 << 19) || ch->C % R != 0 || !prm->kT_host || prm->exchanges < 0 || prm->generations < 0 ||
         prm->trials < 0 || !(prm->p_mut >= 0.0) || (prm->precision != GOAC_FP64 && prm->precision != GOAC_MIXED))
         return fail(ctx, GOAC_EINVAL, "hybrid_round: bad parameters");
     for (int k = 0; k < R; ++k)
@@ -92,6 +105,7 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     goac_problem* pb = ch->pbs[0];
     const int64_t n = pb->d.n, C = ch->C, G = C / R, PC = P + C;
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    GOAC_TRY(rows_check(pb, P, pop_dev, "hybrid_round"));
     // scratch: candidates, their energies, ranks, second population, chain rows
     const size_t b_cand = round_up(PC * n, 256), b_E = round_up(PC * 8, 256), b_idx = round_up(PC * 8, 256);
     const size_t b_cnt = round_up(PC * 4, 256), b_pop = round_up(P * n, 256), b_occ = round_up(C * n, 256);
@@ -106,7 +120,8 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     hipStream_t sm = ctx->stream;
 
     // 1. REMC phase
-    hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, sm, G, R, slot_dev, ch->sc);
+    hipLaunchKernelGGL(k_rows_from_slot, dim3((unsigned)G), dim3(R <= 128 ? 64 : 256), (size_t)((R + 31) / 32) * 4, sm,
+                       G, R, slot_dev, ch->sc);
     GOAC_CHECK_LAUNCH(ctx);
     for (int32_t e = 0; e < prm->exchanges; ++e) {
         if (prm->trials > 0) {
@@ -125,7 +140,7 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     }
     // 2. REMC -> GA: the P lowest of the population and the chains' bests
     GOAC_HIP(ctx, hipMemcpyAsync(cand, pop_dev, (size_t)(P * n), hipMemcpyDeviceToDevice, sm));
-    GOAC_TRY(goac_chains_export(ch, nullptr, cand + P * n, nullptr));
+    GOAC_TRY(chains_export_enqueue(ch, nullptr, cand + P * n, nullptr));
     GOAC_TRY(energies_fp64(pb, PC, cand, Ecand));
     GOAC_TRY(rank_select(ctx, PC, Ecand, (int32_t)P, cnt, idx, nullptr, E_dev));
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)P), dim3(256), 0, sm, P, n, idx, cand, pop_dev);
@@ -142,7 +157,7 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
         gp.n_elite = prm->n_elite;
         gp.p_mut = prm->p_mut;
         GOAC_TRY(ga_generation_enqueue(pb, P, cur, E_dev, &gp, other, k == 0, &ga_err));
-        GOAC_TRY(goac_energies(pb, P, other, (goac_precision)prm->precision, E_dev));
+        GOAC_TRY(energies_enqueue(pb, P, other, (goac_precision)prm->precision, E_dev));
         std::swap(cur, other);
     }
     if (ga_err) GOAC_TRY(ga_check_err(ctx, ga_err));
@@ -150,7 +165,7 @@ extern "C" goac_status goac_hybrid_round(goac_chains* ch, int32_t* slot_dev, int
     // 4. GA -> REMC: the best individuals to the groups' coldest replicas
     const int32_t n_inj = (int32_t)std::max<int64_t>(1, std::min<int64_t>(prm->inject, P));
     GOAC_TRY(rank_select(ctx, P, E_dev, n_inj, cnt, idx, nullptr, nullptr));
-    GOAC_TRY(goac_chains_export(ch, occ_buf, nullptr, nullptr));
+    GOAC_TRY(chains_export_enqueue(ch, occ_buf, nullptr, nullptr));
     hipLaunchKernelGGL(k_inject, dim3((unsigned)G), dim3(256), 0, sm, G, R, n_inj, n, slot_dev, idx, pop_dev, E_dev,
                        ch->sc, occ_buf);
     GOAC_CHECK_LAUNCH(ctx);

@@ -107,10 +107,14 @@ def test_ewald_config5_sampled_and_madelung(ctx):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     assert sym < 1e-13
     ni = 3
+    # a problem whose composition is the ordered arrangement's (every cation Ni2+)
+    all_ni = np.where(cell["sublattice"] >= 0, ni, cell["species"]).astype(np.uint8)
+    pb_ni = G.Problem(ctx, Vg, cell["sublattice"], all_ni, cell["charge"])
+    occ = torch.from_numpy(all_ni[None])
+    E = pb_ni.energies(occ, G.GOAC_FP64).item()
+    Em = pb_ni.energies(occ, G.GOAC_MIXED).item()
+    del pb_ni
     pb = G.Problem(ctx, Vg, cell["sublattice"], cell["species"], cell["charge"])
-    occ = torch.from_numpy(np.where(cell["sublattice"] >= 0, ni, 0).astype(np.uint8)[None])
-    E = pb.energies(occ, G.GOAC_FP64).item()
-    Em = pb.energies(occ, G.GOAC_MIXED).item()
     n = len(cell["pos"])
     closed = -1.74756459463 * O.coulomb_constant() * 4.0 * (n / 2) / 2.1
     assert abs(E - closed) / n < 1e-8

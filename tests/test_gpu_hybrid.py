@@ -29,10 +29,6 @@ def _integer_pair_matrix(n, seed):
     return np.triu(A) + np.triu(A, 1).T
 
 
-@pytest.mark.skip(reason="aborted once (SIGABRT, no GPU fault) when run right after the GA tests of "
-                         "test_gpu_mc.py in one process; cause: a Context finalized before its Problem in a "
-                         "garbage cycle freed the C context under goac_problem_destroy (heap corruption, fixed "
-                         "by reference-counting the context); not rerun on the GPU since the fix")
 @pytest.mark.parametrize("prec", [0, 1])
 def test_hybrid_rounds_match_oracle(ctx, prec):
     cell = S.config2()

@@ -172,3 +172,54 @@ def test_remc_exchange_acceptance_rule():
     # odd steps pair (1, 2), (3, 4), ...
     slot, acc = O.remc_exchange(np.array([0.1, 0.2, 0.3]), np.array([0., 0., 0.]), [0, 1, 2], 1, seed=1)
     assert acc[0] == 0 and acc[1] == 1 and list(slot) == [0, 2, 1]
+
+
+def _stats_view(st):
+    """The chains' counters as a numpy structured view (no copy)."""
+    dt = np.dtype([(f, np.uint64 if t is O.C.c_uint64 else np.float64) for f, t in O.ChainStats._fields_])
+    return np.frombuffer(memoryview(st.stats).cast("B"), dtype=dt)
+
+
+def remc_rounds(cell, V, ladder, groups, rounds, trials, seed):
+    """Replica exchange by the oracle's pieces: every round each chain runs
+    `trials` trials at the temperature of its slot, then exchange step x in every
+    group of R consecutive chains. Returns the final state and slots."""
+    R = len(ladder)
+    st = O.MCState(O.init_occupations(cell, R * groups, seed=seed))
+    slot = np.tile(np.arange(R, dtype=np.int32), (groups, 1))
+    base = (np.arange(groups) * R)[:, None]
+    for x in range(rounds):
+        rows = np.empty(R * groups, np.int32)
+        rows[(base + slot).ravel()] = np.tile(np.arange(R, dtype=np.int32), groups)
+        O.mc_run(V, cell, st, seed=seed, n_trials=trials, kT=np.asarray(ladder)[:, None], block_len=trials,
+                 kT_row=rows)
+        E = _stats_view(st)["E"].copy()
+        for g in range(groups):
+            slot[g], _ = O.remc_exchange(ladder, E[g * R:(g + 1) * R], slot[g], x, seed, group=g)
+    return st, slot
+
+
+def test_remc_stationary_distribution(cfg1):
+    """Replica exchange leaves the product of the ladder's Boltzmann distributions
+    invariant (SI, "Replica Exchange Monte Carlo"), so the configuration held at
+    temperature k is distributed as exp(-E/kT_k) over the 12870 states of config 1.
+    Many independent groups are run from random starts with few trials between
+    exchanges (the exchanges carry much of the mixing) and sampled right after an
+    exchange step; each temperature's energy levels get a chi-square test."""
+    cell, V, occ, E, table = cfg1
+    ladder = np.array([0.4, 0.8, 1.6, 3.2])
+    groups = 1500
+    st, slot = remc_rounds(cell, V, ladder, groups, rounds=300, trials=8, seed=21)
+    levels, inv = np.unique(np.round(E, 6), return_inverse=True)
+    lvl_of = {r.tobytes(): i for r, i in zip(occ, inv)}
+    for k, kT in enumerate(ladder):
+        held = st.occ[np.arange(groups) * len(ladder) + slot[:, k]]
+        obs = np.bincount([lvl_of[o.tobytes()] for o in held], minlength=len(levels))
+        w = np.exp(-(E - E.min()) / kT)
+        exp_ = np.bincount(inv, weights=w) / w.sum() * groups
+        big = exp_ >= 10
+        o2 = np.r_[obs[big], obs[~big].sum()]
+        e2 = np.r_[exp_[big], exp_[~big].sum()]
+        if e2[-1] == 0:
+            o2, e2 = o2[:-1], e2[:-1]
+        assert stats.chisquare(o2, e2).pvalue > 1e-4, "temperature %g" % kT
