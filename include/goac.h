@@ -168,6 +168,22 @@ goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64_t seed, ui
 goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
                           goac_precision prec, double* E_dev);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): goac_energies with the same
+ * kernels and results, its scratch taken from a fixed 32 MiB device array that
+ * every GPU the library runs on holds until the process ends. No device or pinned
+ * memory is allocated. The call waits for the stream (it reads the row check back
+ * into host memory of its own stack).
+ *   Limit: the energies of P rows must fit the array (about P x M x 2 bytes plus
+ *   partial sums for GOAC_MIXED, P x M x 16 bytes plus split-K partials for
+ *   GOAC_FP64); larger calls return EINVAL and compute nothing.
+ *   Concurrency: all calls on one GPU share its array, which keeps the last call's
+ *   contents; calls that overlap on one GPU (other host threads, other streams)
+ *   race and are not allowed.
+ * Errors: as goac_energies (EINVAL for a broken row, E_dev then unchanged). */
+goac_status goac_energies_noalloc(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
+                                  goac_precision prec, double* E_dev);
+
 /* Tile of the GOAC_MIXED population product for populations of P rows: kt n-tiles
  * of 128 positions per K block (1, 2, 4 or 8, at most the problem's number of
  * n-tiles unless 1; 0 returns P to the built-in cost model). The energies differ

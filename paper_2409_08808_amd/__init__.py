@@ -74,7 +74,7 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
             "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
             "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run", "goac_ga_run", "goac_energies_tile",
-            "goac_energies_autotune"]
+            "goac_energies_autotune", "goac_energies_noalloc"]
 
 
 def load():
@@ -97,6 +97,7 @@ def load():
         "goac_problem_get_info": ([P, P], I32),
         "goac_init_occupations": ([P, I64, U64, U32, U32, P], I32),
         "goac_energies": ([P, I64, P, I32, P], I32),
+        "goac_energies_noalloc": ([P, I64, P, I32, P], I32),
         "goac_topk_fp64": ([P, I64, P, I32, P, P], I32),
         "goac_chains_create": ([P, I64, P, I32, U32, U32, P], I32),
         "goac_chains_destroy": ([P], None),
@@ -229,6 +230,13 @@ class Problem:
         E = out if out is not None else torch.empty(P, dtype=torch.float64, device=self.ctx.device)
         self.ctx.check(load().goac_energies(self._h, P, _ptr(occ), precision, _ptr(E)))
         return E
+
+    def energies_noalloc(self, occ, precision, out):
+        """goac_energies_noalloc: energies of occ (P x n, device uint8) into out (P
+        doubles, device), with no allocation by the library or here."""
+        P = occ.shape[0]
+        self.ctx.check(load().goac_energies_noalloc(self._h, P, _ptr(occ), precision, _ptr(out)))
+        return out
 
     def energies_tile(self, P, kt):
         """Set the mixed population product's tile for P rows (0: the cost model)."""

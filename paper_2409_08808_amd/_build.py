@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgoac.so")
 OBJ = os.path.join(HERE, "_objs")
-SOURCES = ["api.hip", "ewald.hip", "gemm.hip", "mc.hip", "ga.hip", "gd.hip", "hybrid.hip"]
+SOURCES = ["api.hip", "ewald.hip", "gemm.hip", "mc.hip", "ga.hip", "gd.hip", "hybrid.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -528,17 +528,23 @@ static goac_status check_publish(goac_ctx* ctx) {
     return GOAC_OK;
 }
 
+goac_status rows_check_launch(goac_problem* pb, int64_t P, const uint8_t* occ, int32_t* flag) {
+    goac_ctx* ctx = pb->ctx;
+    if (P < 0 || P > ((int64_t)1 << 30) || (P > 0 && !occ)) return fail(ctx, GOAC_EINVAL, "row check: bad rows");
+    const ProblemDev& d = pb->d;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, flag, 1);
+    if (P > 0)
+        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)P), dim3(256), 0, ctx->stream, d.n, d.M, d.S, d.E, d.tab,
+                           d.mob, d.msub, occ, flag);
+    GOAC_CHECK_LAUNCH(ctx);
+    return GOAC_OK;
+}
+
 goac_status rows_check_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ) {
     goac_ctx* ctx = pb->ctx;
     if (ctx->capturing) return fail(ctx, GOAC_EINVAL, "row check inside a stream capture");
-    if (P < 0 || P > ((int64_t)1 << 30) || (P > 0 && !occ)) return fail(ctx, GOAC_EINVAL, "row check: bad rows");
     GOAC_TRY(check_buffers(ctx));
-    const ProblemDev& d = pb->d;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ctx->chk_dev, 1);
-    if (P > 0)
-        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)P), dim3(256), 0, ctx->stream, d.n, d.M, d.S, d.E, d.tab,
-                           d.mob, d.msub, occ, ctx->chk_dev);
-    GOAC_CHECK_LAUNCH(ctx);
+    GOAC_TRY(rows_check_launch(pb, P, occ, ctx->chk_dev));
     return check_publish(ctx);
 }
 
@@ -604,6 +610,11 @@ extern "C" goac_status goac_ctx_create(int device, void* hip_stream, goac_ctx** 
     ctx->dev.stream = ctx->stream;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    // the device address of the allocation-free entry point's scratch array
+    if (noalloc_setup(device) != hipSuccess) {
+        delete ctx;
+        return GOAC_EHIP;
+    }
     *out = ctx;
     return GOAC_OK;
 }

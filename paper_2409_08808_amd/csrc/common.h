@@ -334,6 +334,22 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
 // scratch memory of a context (grown, never shrunk)
 goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out);
 
+// Where a call takes its scratch: the context's workspace slots (base null), or a
+// block the caller provides, carved in request order at 256-byte alignment.
+struct WsSource {
+    goac_ctx* ctx = nullptr;
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+    goac_status get(int slot, size_t bytes, void** out) {
+        if (!base) return workspace(ctx, slot, bytes, out);
+        const size_t o = (off + 255) / 256 * 256;
+        if (o + bytes > cap) return fail(ctx, GOAC_EINVAL, "scratch block too small");
+        *out = base + o;
+        off = o + bytes;
+        return GOAC_OK;
+    }
+};
+
 // arenas of problems and chain sets: a block released to the context is handed to
 // the next arena that fits in it (at most twice its size); *bytes is rounded up
 goac_status pool_get(goac_ctx* ctx, size_t* bytes, void** out);
@@ -358,9 +374,14 @@ inline goac_status rows_check(goac_problem* pb, int64_t P, const uint8_t* occ, c
 // by (E, index); cnt_scratch holds P int32. With a gate, the kernels that read the
 // rows and write E do nothing while *gate is non-zero (rows a check rejected).
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt = 0,
-                           const int32_t* gate = nullptr);
+                           const int32_t* gate = nullptr, WsSource* ws = nullptr);
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E,
-                          const int32_t* gate = nullptr);
+                          const int32_t* gate = nullptr, WsSource* ws = nullptr);
+// scratch bytes (with the 256-byte alignment of WsSource) that energies of P rows take
+size_t energies_scratch_bytes(const goac_problem* pb, int64_t P, goac_precision prec);
+// launch of the composition check of P rows, or-ing a broken row into *flag
+// (cleared first by the launch)
+goac_status rows_check_launch(goac_problem* pb, int64_t P, const uint8_t* occ, int32_t* flag);
 // copies of the chains' occupations, best occupations and counters (any may be
 // null), queued on the stream without a wait
 goac_status chains_export_enqueue(goac_chains* ch, uint8_t* occ, uint8_t* best, goac_chain_stats* stats);
@@ -377,6 +398,11 @@ goac_status rank_select(goac_ctx* ctx, int64_t P, const double* E, int32_t k, in
 // C = alpha A B^T + beta C (FP64); sym: A = B and M = N, upper tiles computed and mirrored
 goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
-                     const int32_t* M_dev, bool sym = false);
+                     const int32_t* M_dev, bool sym = false, WsSource* ws = nullptr);
+// Looks up, once per device and with that device current, the device address of
+// the allocation-free entry point's scratch array (noalloc.hip).
+hipError_t noalloc_setup(int device);
+// K splits of that product (its partials take splits x M x N doubles when > 1)
+int dgemm_splits(const goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const int32_t* M_dev, bool sym);
 
 }  // namespace goac

@@ -127,24 +127,29 @@ __global__ void k_dgemm_reduce(int64_t M, int64_t N, int32_t splits, const doubl
     *o = (beta == 0.0) ? val : val + beta * *o;
 }
 
-goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
-                     const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
-                     const int32_t* M_dev, bool sym) {
-    if (M <= 0 || N <= 0) return GOAC_OK;
-    if (sym && (M != N || A != B || lda != ldb || M_dev))
-        return fail(ctx, GOAC_EINVAL, "dgemm_nt: a symmetric product needs A = B and M = N");
+// split K when the tile grid leaves most compute units idle and K is long
+int dgemm_splits(const goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const int32_t* M_dev, bool sym) {
     const int64_t tn = (N + DG_BN - 1) / DG_BN;
     const int64_t tiles = sym ? tn * (tn + 1) / 2 : tn * ((M + DG_BM - 1) / DG_BM);
-    // split K when the tile grid leaves most compute units idle and K is long
     int splits = 1;
     const int64_t want = 2 * (int64_t)ctx->num_cus;
     while (!M_dev && tiles * splits < want && K / (splits * 2) >= 256 && splits < 32) splits *= 2;
+    return splits;
+}
+
+goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                     const int32_t* M_dev, bool sym, WsSource* ws) {
+    if (M <= 0 || N <= 0) return GOAC_OK;
+    if (sym && (M != N || A != B || lda != ldb || M_dev))
+        return fail(ctx, GOAC_EINVAL, "dgemm_nt: a symmetric product needs A = B and M = N");
+    const int splits = dgemm_splits(ctx, M, N, K, M_dev, sym);
     const int64_t kps = round_up((K + splits - 1) / splits, DG_BK);
     double* part = nullptr;
     if (splits > 1) {
+        WsSource own{ctx};
         void* w = nullptr;
-        goac_status st = workspace(ctx, 1, (size_t)splits * M * N * sizeof(double), &w);
-        if (st != GOAC_OK) return st;
+        GOAC_TRY((ws ? ws : &own)->get(1, (size_t)splits * M * N * sizeof(double), &w));
         part = (double*)w;
     }
     dim3 grid((unsigned)((N + DG_BN - 1) / DG_BN), (unsigned)((M + DG_BM - 1) / DG_BM), (unsigned)splits);
@@ -512,9 +517,10 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
     return GOAC_OK;
 }
 
-goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req,
-                           const int32_t* gate) {
-    goac_ctx* ctx = pb->ctx;
+// n-tiles per K block of the mixed product for P rows and the number of (n-tile,
+// K block) pairs it forms: the requested KT, else the one set or tuned for this
+// population size, else the one that minimises the estimated makespan
+static int32_t pop_kt_choice(const goac_problem* pb, int64_t P, int32_t kt_req, int64_t* n_pairs) {
     const ProblemDev& d = pb->d;
     const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
     const int64_t MT = (P + PB_BM - 1) / PB_BM;
@@ -540,7 +546,7 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
         int64_t best_cost = -1;
         for (int kt = 1; kt <= 8 && (kt == 1 || kt <= NT); kt *= 2) {
             const int64_t wg = MT * pairs(kt);
-            const int64_t rounds = (wg + 2 * ctx->num_cus - 1) / (2 * ctx->num_cus);
+            const int64_t rounds = (wg + 2 * pb->ctx->num_cus - 1) / (2 * pb->ctx->num_cus);
             const int64_t cost = rounds * ((int64_t)kt * PB_BN + 128);
             if (best_cost < 0 || cost <= best_cost) {
                 best_cost = cost;
@@ -548,14 +554,40 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
             }
         }
     }
-    const int64_t total = MT * pairs(KT);
+    *n_pairs = pairs(KT);
+    return KT;
+}
+
+size_t energies_scratch_bytes(const goac_problem* pb, int64_t P, goac_precision prec) {
+    const ProblemDev& d = pb->d;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    if (prec == GOAC_MIXED) {
+        int64_t n_parts = 0;
+        (void)pop_kt_choice(pb, P, 0, &n_parts);
+        const size_t dq_bytes = al((size_t)P * d.Mp * sizeof(__hip_bfloat16));
+        const size_t part_bytes = al((size_t)P * n_parts * sizeof(double));
+        return al(dq_bytes + part_bytes + (size_t)P * sizeof(double));
+    }
+    const size_t qb = al((size_t)P * d.Mp * sizeof(double));
+    const int splits = dgemm_splits(pb->ctx, P, d.M, d.Mp, nullptr, false);
+    return al(2 * qb) + (splits > 1 ? al((size_t)splits * P * d.M * sizeof(double)) : 0);
+}
+
+goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req,
+                           const int32_t* gate, WsSource* src) {
+    goac_ctx* ctx = pb->ctx;
+    const ProblemDev& d = pb->d;
+    const int64_t MT = (P + PB_BM - 1) / PB_BM;
+    int64_t n_pairs = 0;
+    const int32_t KT = pop_kt_choice(pb, P, kt_req, &n_pairs);
+    const int64_t total = MT * n_pairs;
     if (total > ((int64_t)1 << 30)) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
-    const int32_t n_parts = (int32_t)pairs(KT);
+    const int32_t n_parts = (int32_t)n_pairs;
     const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
     const size_t part_bytes = round_up((size_t)P * n_parts * sizeof(double), 256);
+    WsSource own{ctx};
     void* ws = nullptr;
-    goac_status st = workspace(ctx, 0, dq_bytes + part_bytes + (size_t)P * sizeof(double), &ws);
-    if (st != GOAC_OK) return st;
+    GOAC_TRY((src ? src : &own)->get(0, dq_bytes + part_bytes + (size_t)P * sizeof(double), &ws));
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
     double* part = (double*)((char*)ws + dq_bytes);
     double* lin = nullptr;
@@ -588,17 +620,19 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
     return GOAC_OK;
 }
 
-goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, const int32_t* gate) {
+goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, const int32_t* gate,
+                          WsSource* src) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const size_t qb = round_up((size_t)P * d.Mp * sizeof(double), 256);
+    WsSource own{ctx};
     void* ws = nullptr;
-    goac_status st = workspace(ctx, 0, 2 * qb, &ws);
+    goac_status st = (src ? src : &own)->get(0, 2 * qb, &ws);
     if (st != GOAC_OK) return st;
     double* Q = (double*)ws;
     double* Phi = (double*)((char*)ws + qb);
     GOAC_TRY(build_q64(ctx, P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.charge, Q, gate));
-    st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr);
+    st = dgemm_nt(ctx, P, d.M, d.Mp, Q, d.Mp, d.V64, d.Mp, Phi, d.Mp, 1.0, 0.0, nullptr, false, src);
     if (st != GOAC_OK) return st;
     hipLaunchKernelGGL(k_pop_fp64_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M,
                        d.Mp, Q, Phi, d.h, d.Ed, E, gate);
