@@ -149,6 +149,37 @@ def cell_matrix(cell):
     return ewald_matrix(cell["lattice"], cell["pos"], e["alpha"], e["rcut"], e["kmax"])
 
 
+def grid_matrix(cell):
+    """The pair matrix of a cell whose sites fill a whole grid of its lattice (a
+    conventional rock-salt supercell: cations and anions together form the simple
+    cubic grid of spacing a/2), from one row. Every Ewald entry is a sum over the
+    lattice images of r_j - r_i, so it depends only on r_j - r_i modulo the lattice,
+    and V_ij = V_0k for the site k at r_0 + r_j - r_i. Row 0 is computed entry by
+    entry (the plain definition); the rest is that relabelling. For cells whose
+    entry-by-entry matrix takes too long; pinned against it on smaller cells.
+    Raises ValueError when the sites are not a whole grid."""
+    lat = np.asarray(cell["lattice"], np.float64)
+    pos = np.asarray(cell["pos"], np.float64)
+    n = len(pos)
+    frac = np.linalg.solve(lat.T, pos.T).T % 1.0
+    D = np.array([len(np.unique(np.round(frac[:, a] * 2 ** 20).astype(np.int64) % 2 ** 20)) for a in range(3)])
+    g = np.round(frac * D).astype(np.int64) % D
+    if int(np.prod(D)) != n or np.abs(frac * D - np.round(frac * D)).max() > 1e-6:
+        raise ValueError("the sites do not fill a grid of the lattice")
+    flat = lambda d: (d[..., 0] * D[1] + d[..., 1]) * D[2] + d[..., 2]
+    site_of = np.full(n, -1, np.int64)
+    site_of[flat((g - g[0]) % D)] = np.arange(n)
+    if (site_of < 0).any():
+        raise ValueError("the sites do not fill a grid of the lattice")
+    e = cell["ewald"]
+    row = np.array([ewald_entry(lat, pos, 0, j, e["alpha"], e["rcut"], e["kmax"]) for j in range(n)])
+    V = np.empty((n, n), np.float64)
+    for i0 in range(0, n, 512):
+        d = (g[None, :, :] - g[i0:i0 + 512, None, :]) % D
+        V[i0:i0 + 512] = row[site_of[flat(d)]]
+    return V
+
+
 # ---------------------------------------------------------------- energies
 
 def energy_q(V, q):

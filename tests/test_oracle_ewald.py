@@ -169,3 +169,22 @@ def test_defaults_rule():
     assert abs(a - 5 / 16.8) < 1e-15 and abs(rc - 6 / a) < 1e-12 and k == 10
     a, rc, k = O.ewald_defaults(S.config5()["lattice"])
     assert k == 13
+
+
+@pytest.mark.parametrize("reps", [(2, 2, 1), (2, 2, 2), (3, 2, 1)])
+def test_grid_matrix_equals_entry_by_entry(reps):
+    """The pair matrix of a rock-salt cell relabelled from its first row equals
+    the entry-by-entry matrix (translation invariance of every Ewald entry)."""
+    lat, pos, kind = S.rocksalt_conventional(*reps, 4.2)
+    cell = S.make_cell(lat, pos, np.where(kind == 0, 0, -1), np.where(kind == 0, 1, 0).astype(np.uint8),
+                       [-2.0, 2.0], ["O", "M"])
+    full = O.cell_matrix(cell)
+    fast = O.grid_matrix(cell)
+    assert np.abs(fast - full).max() <= 1e-12 * np.abs(full).max()
+
+
+def test_grid_matrix_refuses_other_cells():
+    lat, pos, kind = S.spinel_primitive(1, 1, 1, 8.1)
+    cell = S.make_cell(lat, pos, np.full(len(pos), -1, np.int32), np.zeros(len(pos), np.uint8), [0.0], ["X"])
+    with pytest.raises(ValueError):
+        O.grid_matrix(cell)
