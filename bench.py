@@ -1,21 +1,25 @@
 """Benchmark of the Coulomb cluster-expansion hot path on one MI355X.
 
 A step is one pass of the whole path over one batch of synthetic input, the
-4x4x4 rock-salt supercell (N = 512; 256 O2- fixed; Li+ 128, Ni2+ 32, Co3+ 64,
-Mn4+ 32 on 256 cation positions):
+16x16x8 rock-salt supercell (N = 16384: 8192 O2- fixed and 8192 cation positions
+of Li+/Na+/Ni2+/Co3+/Mn4+/Ti4+ in charge-neutral proportions):
   1. FP64 Ewald pair matrix (real-space erfc + reciprocal sum on matrix cores)
   2. problem derivation (mobile block in FP64/FP32/bf16 hi+lo, fixed-ion field)
-  3. 4096 random starts, 4096 chains
-  4. 4096 chains x 1e5 swap trials, kT 0.5 -> 0.01 eV geometric over 100 blocks
-     of 1000 trials; FP32 field with FP64 re-anchoring every 1024 field updates
-  5. energies of the 4096 best occupations (bf16 hi+lo matrix-core product)
-  6. one GA generation on them (8 elites, mutation rate 0.2)
-  7. FP64 top-64 of the 4096 best occupations
-value = swap trials per second over whole steps (inputs resident on the GPU).
+  3. 8192 random starts, 8192 chains
+  4. 8192 chains x 1e5 swap trials, kT 0.5 -> 0.01 eV geometric over 100 blocks
+     of 1000 trials; FP32 field with batched FP64 re-anchoring after 1024 field
+     updates (between chunks of 8192 trials)
+  5. a GA population of 512 (random starts), 100 generations, each followed by
+     the children's energies on the bf16 hi+lo matrix-core product
+  6. FP64 top-64 of the GA population and the 8192 chain bests
+value = swap trials per second over whole steps (the cell's positions and
+composition are host inputs of 0.4 MB; everything else lives on the GPU).
 
-Also measured: the same step with the FP64 field and FP64 energies ("plain
-FP64"), and population energies per second of the GA workload (8x8x8 rock-salt,
-N = 4096, P = 1024, 200 generations: bf16 hi+lo energies, GA generation).
+Also measured, as extra keys: the same step in plain FP64 (FP64 field and
+energies, default launches); energies per second at configs 1, 3 and 5 (mixed
+against FP64); the 4x4x4 cell's 4096-chain step; config 1's 64-chain run; the
+512 uneven instances in one persistent autotuned launch against per-instance
+FP64 launches; the NaCl, gradient-descent, replica-exchange and hybrid legs.
 """
 import argparse
 import json
@@ -29,37 +33,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MC swap-trials/s and config energies/s, mixed+batched vs plain FP64, 1 GPU"
-CHAINS, TRIALS, BLOCKS, BLOCK_LEN = 4096, 100000, 100, 1000
+C5, T5, BLOCKS, BLOCK_LEN = 8192, 100000, 100, 1000
+P5, GENS5, TOPK = 512, 100, 64
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit or FP64 VALU lane operations per second
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 BF16_PEAK = 2.5e15
-# HBM bytes of one k_mc<mixed, 64> launch of this step from FETCH_SIZE and WRITE_SIZE,
-# each scaled by the same counter's reading for a 256 MiB copy (factors 2.0 and 1.0);
-# valid only for the kernel sources they were taken on (profiles/k_mc_rocksalt4x4x4_traffic.md)
-MC_TRAFFIC = {"bytes": 46128444.0,
+FP64_PEAK = 78.6e12
+# HBM bytes per k_mc<mixed, 256> launch of the step's sweep from FETCH_SIZE and
+# WRITE_SIZE, each scaled by the same counter's reading for a plain copy of known
+# size; valid only for the kernel sources they were taken on
+MC_TRAFFIC = {"bytes": None,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": "5d02a610c58232fd30f5d87930668adfcee22d9f121e06898af616cd51492ea1"}
+              "sha256": ""}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the plain-FP64 and GA-energies legs")
+    ap.add_argument("--no-extras", action="store_true", help="only the step")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a copy kernel of known size")
     ap.add_argument("--ga-generations", type=int, default=200)
-    ap.add_argument("--no-large", action="store_true", help="skip the 16384-site and 512-instance legs")
-    ap.add_argument("--only", default="", help="comma list of legs to run alone: fp64, ga, cfg5, cfg4, nacl, "
-                                                "gd, remc, hybrid (the step itself always runs)")
+    ap.add_argument("--only", default="", help="comma list of extra legs: fp64, energies, cfg1, cfg2, ga, cfg4, "
+                                                "nacl, gd, remc, hybrid (the step itself always runs)")
     return ap.parse_args()
 
 
 def measured_traffic(entry):
     """The counter-based traffic figure, or None once its kernel sources changed."""
     import hashlib
+    if entry["bytes"] is None:
+        return None
     h = hashlib.sha256()
     for f in entry["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -73,6 +80,16 @@ def algorithmic_ops(trials, updates, M):
     the uniform 4, dE 10, the Metropolis test 20 (one logarithm); a field update
     2 fused multiply-adds per mobile position."""
     return trials * 118.0 + updates * 2.0 * M
+
+
+def pop_flops(P, M):
+    """Algorithmic flops of the energies of P rows (Eq. 2's quadratic form): 2 M^2
+    + 4 M per row (the product with V_mm, the row dot, the linear term)."""
+    return P * (2.0 * M * M + 4.0 * M)
+
+
+def ev(torch):
+    return torch.cuda.Event(enable_timing=True)
 
 
 def main():
@@ -91,53 +108,54 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     ctx = G.Context(0, stream)
-    cell = S.config2()
+    cell = S.config5()
     kT = np.geomspace(0.5, 0.01, BLOCKS)
+    M = int((cell["sublattice"] >= 0).sum())
 
-    def step(seed, prec, ev=None, host_stats=False):
+    def step(seed, prec, timing=False, host_stats=False):
+        """One pass of the path; prec GOAC_MIXED (FP32 field, bf16 hi+lo energies) or
+        GOAC_FP64 (FP64 field and energies, the size rule's launch)."""
         V = ctx.build_ewald(cell["lattice"], cell["pos"])
         pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
-        occ0 = pb.init_occupations(CHAINS, seed=seed)
+        del V
+        occ0 = pb.init_occupations(C5, seed=seed)
         ch = G.Chains(pb, occ0, prec)
-        if ev is not None:
-            ev[0].record(stream)
-        ch.sweep(TRIALS, kT, BLOCK_LEN, seed=seed, reanchor_every=1024)
-        if ev is not None:
-            ev[1].record(stream)
-        occ, best, stats = ch.export(host_stats=host_stats)
-        best = best.view(CHAINS, -1)
-        E = pb.energies(best, G.GOAC_MIXED if prec == G.GOAC_MIXED else G.GOAC_FP64)
-        pb.ga_generation(best, E, seed=seed, generation=0, n_elite=8, p_mut=0.2)
-        idx, Ek = pb.topk(best, 64)
-        # no wait here: releases are stream-ordered, so the next step's host work
-        # overlaps this step's last kernels
+        del occ0
+        ch.sweep(T5, kT, BLOCK_LEN, seed=seed, reanchor_every=1024, timing=timing)
+        pop = pb.init_occupations(P5, seed=seed, chain_base=1 << 20)
+        E = pb.energies(pop, prec)
+        pb.ga_run(pop, E, seed=seed, generation=0, generations=GENS5, n_elite=8, p_mut=0.2, precision=prec)
+        _, best, stats = ch.export(host_stats=host_stats, occ=False)
+        cand = torch.cat([pop, best])
+        idx, Ek = pb.topk(cand, TOPK)
+        tm = ch.timing() if timing else None
         ch.close()
         pb.close()
-        return stats
+        return stats, tm, Ek
 
     def timed(prec, steps, warmup):
         for w in range(warmup):
             step(1000 + w, prec)
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
-        stats = None
+        stats, tms, Ek = None, [], None
         for k in range(steps):
-            stats = step(k, prec, evs[k], host_stats=(k == steps - 1))
+            stats, tm, Ek = step(k, prec, timing=True, host_stats=(k == steps - 1))
+            tms.append(tm)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        kern = np.array([a.elapsed_time(b) for a, b in evs]) * 1e-3
-        print("  [%s] %d steps in %.3f s; sweep %.2f ms avg" % ("mixed" if prec else "fp64", steps, wall,
-                                                               1e3 * kern.mean()), file=sys.stderr, flush=True)
-        return wall, kern, stats
+        print("  [step %s] %d steps in %.3f s" % ("mixed" if prec else "fp64", steps, wall), file=sys.stderr,
+              flush=True)
+        return wall, tms, stats, Ek
 
-    wall, kern, stats = timed(G.GOAC_MIXED, args.steps, args.warmup)
-    total_trials = float(CHAINS) * TRIALS * args.steps
-    value = total_trials / wall
-    M = 256
+    wall, tms, stats, Ek = timed(G.GOAC_MIXED, args.steps, args.warmup)
+    value = float(C5) * T5 * args.steps / wall
     upd = float(stats["updates"].sum())
-    ops = algorithmic_ops(float(CHAINS) * TRIALS, upd, M)
-    achieved = ops / kern.mean()
+    mc_s = np.mean([t[0] for t in tms])
+    anchor_s = np.mean([t[1] for t in tms])
+    launches = tms[-1][2]
+    row_bytes = upd * 2.0 * M * 4.0            # two FP32 rows of V_mm per field update
+    achieved = row_bytes / mc_s / 1e9
     result = {
         "metric": METRIC,
         "value": value,
@@ -149,33 +167,49 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64+bf16",
         "data": "synthetic",
-        "config": {"workload": "rock-salt 4x4x4 (N=512, M=256; Li/Ni/Co/Mn 128/32/64/32), 4096 chains x 1e5 "
-                               "trials, kT 0.5->0.01 eV over 100 blocks, FP32 field + FP64 re-anchor/1024, "
-                               "then bf16 energies, GA generation and FP64 top-64 of the chain bests",
-                   "chains": CHAINS, "trials_per_chain": TRIALS, "parallelism": "chains per workgroup"},
-        "mc_sweep_ms": 1e3 * kern.mean(),
-        "mc_trials_per_s_kernel": CHAINS * TRIALS / kern.mean(),
-        "accept_rate": float(stats["accepts"].sum()) / (CHAINS * TRIALS),
-        "field_updates_per_chain": upd / CHAINS,
-        "fallbacks_per_chain": float(stats["fallbacks"].sum()) / CHAINS,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": measured_traffic(MC_TRAFFIC),
-                     "kernel": "k_mc<mixed>", "ops_per_launch": ops},
+        "config": {"workload": "rock-salt 16x16x8 (N=16384, M=8192; Li/Na/Ni/Co/Mn/Ti, charge-neutral units), "
+                               "Ewald + problem, 8192 chains x 1e5 trials, kT 0.5->0.01 eV over 100 blocks, FP32 "
+                               "field + batched FP64 re-anchor/1024, GA P=512 x 100 generations with bf16 hi+lo "
+                               "energies, FP64 top-64 of the GA population and the chain bests",
+                   "chains": C5, "trials_per_chain": T5, "ga_population": P5, "ga_generations": GENS5,
+                   "topk": TOPK, "parallelism": "chains per workgroup, populations on matrix cores"},
+        "mc_sweep_kernel_s": mc_s,
+        "mc_anchor_s": anchor_s,
+        "mc_launches_per_sweep": launches,
+        "mc_trials_per_s_kernel": C5 * T5 / mc_s,
+        "accept_rate": float(stats["accepts"].sum()) / (C5 * T5),
+        "field_updates_per_chain": upd / C5,
+        "fallbacks_per_chain": float(stats["fallbacks"].sum()) / C5,
+        "anchors_per_chain": float(stats["anchors"].sum()) / C5,
+        "best_E_topk_min": float(Ek.min().item()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(MC_TRAFFIC),
+                     "kernel": "k_mc<mixed,256>", "launches": launches,
+                     "bytes_per_launch": row_bytes / launches, "launch_s": mc_s / launches},
     }
     legs = set(args.only.split(",")) - {""}
     if not legs and not args.no_extras:
-        legs = {"fp64", "ga", "nacl", "gd", "remc", "hybrid"} | (set() if args.no_large else {"cfg5", "cfg4"})
+        legs = {"fp64", "energies", "cfg1", "cfg2", "ga", "cfg4", "nacl", "gd", "remc", "hybrid"}
     if "fp64" in legs:
-        w64, k64, s64 = timed(G.GOAC_FP64, max(2, args.steps // 2), 1)
-        result["plain_fp64_trials_per_s"] = float(CHAINS) * TRIALS * max(2, args.steps // 2) / w64
-        result["plain_fp64_sweep_ms"] = 1e3 * k64.mean()
+        n64 = max(1, min(2, args.steps))
+        w64, tm64, s64, _ = timed(G.GOAC_FP64, n64, 1)
+        result["plain_fp64_trials_per_s"] = float(C5) * T5 * n64 / w64
+        result["plain_fp64_ms_per_step"] = 1e3 * w64 / n64
+        result["plain_fp64_sweep_kernel_s"] = np.mean([t[0] for t in tm64])
+        upd64 = float(s64["updates"].sum())
+        result["plain_fp64_field_update_GBs"] = upd64 * 2.0 * M * 8.0 / result["plain_fp64_sweep_kernel_s"] / 1e9
         result["mixed_vs_fp64"] = result["value"] / result["plain_fp64_trials_per_s"]
+        result["mixed_vs_fp64_sweep"] = result["plain_fp64_sweep_kernel_s"] / mc_s
+    if "energies" in legs:
+        result.update(energies_legs(ctx, G, S, torch, stream))
+    if "cfg1" in legs:
+        result.update(config1(ctx, G, S, torch, stream))
+    if "cfg2" in legs:
+        result.update(config2_step(ctx, G, S, torch, stream, max(2, args.steps)))
     if "ga" in legs:
         result.update(ga_energies(ctx, G, S, torch, stream, args.ga_generations))
-    if "cfg5" in legs:
-        result.update(large_cell(ctx, G, S, torch, stream))
     if "cfg4" in legs:
         result.update(batched_instances(ctx, G, S, torch, stream))
     if "nacl" in legs:
@@ -194,54 +228,133 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = 2 * x.numel()
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(S)
+        result["cpu_baseline"] = cpu_baseline(S, kT)
     print(json.dumps(result), flush=True)
 
 
+def timed_calls(torch, stream, fn, reps):
+    """Mean device seconds of fn() over reps calls (HIP events on the stream)."""
+    fn()
+    a, b = ev(torch), ev(torch)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
+def energies_legs(ctx, G, S, torch, stream):
+    """Population energies per second, mixed (bf16 hi+lo, FP32 accumulation) and
+    FP64, on the 16x16x8 cell with the GA's 512 rows and on the 8x8x8 cell with
+    1024 rows (calls back to back, each with its row check)."""
+    out = {}
+    for name, cfg, P in (("cfg5", S.config5, 512), ("cfg3", S.config3, 1024)):
+        cell = cfg()
+        V = ctx.build_ewald(cell["lattice"], cell["pos"])
+        pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+        del V
+        M = int((cell["sublattice"] >= 0).sum())
+        pop = pb.init_occupations(P, seed=0)
+        E = torch.empty(P, dtype=torch.float64, device=pop.device)
+        for prec, pn in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+            sec = timed_calls(torch, stream, lambda: pb.energies(pop, prec, out=E), 20)
+            out["%s_%s_energies_per_s" % (name, pn)] = P / sec
+            out["%s_%s_energy_call_us" % (name, pn)] = 1e6 * sec
+            peak = BF16_PEAK if prec == G.GOAC_MIXED else FP64_PEAK
+            out["%s_%s_energy_frac_of_peak" % (name, pn)] = pop_flops(P, M) / sec / peak
+        out["%s_energies_mixed_vs_fp64" % name] = (out["%s_mixed_energies_per_s" % name] /
+                                                   out["%s_fp64_energies_per_s" % name])
+        pb.close()
+        print("  [energies %s] mixed %.1f us, fp64 %.1f us" % (name, out["%s_mixed_energy_call_us" % name],
+                                                              out["%s_fp64_energy_call_us" % name]),
+              file=sys.stderr, flush=True)
+    out["energies_per_s"] = out["cfg5_mixed_energies_per_s"]
+    return out
+
+
+def config1(ctx, G, S, torch, stream):
+    """Config 1 (2x2x1 rock-salt, 16 Li+/M3+ positions, alpha = 5/L, r_c = 10 A,
+    |n| <= 8): energies of all 12870 occupations, and 64 chains x 1e4 trials at kT
+    = 0.05 eV, seed 0, mixed against FP64."""
+    cell = S.config1()
+    e = cell["ewald"]
+    V = ctx.build_ewald(cell["lattice"], cell["pos"], e["alpha"], e["rcut"], e["kmax"])
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    occ = torch.from_numpy(S.config1_exhaustive_occupations(cell)).cuda()
+    E = torch.empty(len(occ), dtype=torch.float64, device=occ.device)
+    out = {}
+    for prec, pn in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+        sec = timed_calls(torch, stream, lambda: pb.energies(occ, prec, out=E), 20)
+        out["cfg1_%s_energies_per_s" % pn] = len(occ) / sec
+        occ0 = pb.init_occupations(64, seed=0)
+        ch = G.Chains(pb, occ0, prec)
+        ch.sweep(10000, [0.05], seed=1)
+        ch.timing()
+        ch.sweep(10000, [0.05], seed=0, timing=True)
+        mc, _, _ = ch.timing()
+        out["cfg1_%s_trials_per_s" % pn] = 64 * 10000 / mc
+        ch.close()
+    pb.close()
+    return out
+
+
+def config2_step(ctx, G, S, torch, stream, steps):
+    """The 4x4x4 rock-salt cell (N = 512; Li/Ni/Co/Mn 128/32/64/32): Ewald, problem,
+    4096 chains x 1e5 trials (kT 0.5 -> 0.01 eV, FP32 field + FP64 re-anchor every
+    1024 updates inside the kernel), energies of the bests, one GA generation and
+    the FP64 top-64; mixed against FP64."""
+    cell = S.config2()
+    kT = np.geomspace(0.5, 0.01, BLOCKS)
+    out = {}
+
+    def one(seed, prec):
+        V = ctx.build_ewald(cell["lattice"], cell["pos"])
+        pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+        ch = G.Chains(pb, pb.init_occupations(4096, seed=seed), prec)
+        ch.sweep(100000, kT, BLOCK_LEN, seed=seed, reanchor_every=1024, timing=True)
+        _, best, st = ch.export(host_stats=False, occ=False)
+        E = pb.energies(best, prec)
+        pb.ga_generation(best, E, seed=seed, generation=0, n_elite=8, p_mut=0.2)
+        pb.topk(best, 64)
+        tm = ch.timing()
+        ch.close()
+        pb.close()
+        return tm
+
+    for prec, pn in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
+        one(999, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tms = [one(k, prec) for k in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["cfg2_%s_trials_per_s" % pn] = 4096 * 100000.0 * steps / wall
+        out["cfg2_%s_ms_per_step" % pn] = 1e3 * wall / steps
+        out["cfg2_%s_sweep_ms" % pn] = 1e3 * np.mean([t[0] for t in tms])
+    out["cfg2_mixed_vs_fp64"] = out["cfg2_mixed_trials_per_s"] / out["cfg2_fp64_trials_per_s"]
+    out["cfg2_mixed_vs_fp64_sweep"] = out["cfg2_fp64_sweep_ms"] / out["cfg2_mixed_sweep_ms"]
+    print("  [cfg2] mixed %.2f ms, fp64 %.2f ms per step" % (out["cfg2_mixed_ms_per_step"],
+                                                            out["cfg2_fp64_ms_per_step"]), file=sys.stderr, flush=True)
+    return out
+
+
 def ga_energies(ctx, G, S, torch, stream, generations):
-    """GA workload: 8x8x8 rock-salt (N = 4096), P = 1024, `generations`
-    generations; energies/s counts only the population-energy calls (mixed: with
-    the tile the autotuner picked for this population size)."""
+    """GA workload of the 8x8x8 cell (N = 4096, P = 1024): generations of
+    goac_ga_run (each followed by the children's energies, mixed or FP64), and on
+    the 4x4x4 cell the same generations called one by one from Python against
+    goac_ga_run (graph replays)."""
+    out = {}
     cell = S.config3()
     V = ctx.build_ewald(cell["lattice"], cell["pos"])
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
     del V
-    out = {}
-    for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
-        pop = pb.init_occupations(1024, seed=0)
-        E = torch.empty(1024, dtype=torch.float64, device=pop.device)
-        if prec == G.GOAC_MIXED:
-            out["ga_mixed_tile_autotuned"] = pb.energies_autotune(pop)
-        pb.energies(pop, prec, out=E)                      # warm-up
-        torch.cuda.synchronize()
-        t_en = 0.0
-        t0 = time.perf_counter()
-        gens = generations if prec == G.GOAC_MIXED else max(10, generations // 10)
-        for g in range(gens):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            pb.energies(pop, prec, out=E)
-            b.record(stream)
-            pop = pb.ga_generation(pop, E, seed=0, generation=g, n_elite=8, p_mut=0.2)
-            b.synchronize()
-            t_en += a.elapsed_time(b) * 1e-3
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out["ga_%s_energies_per_s" % name] = 1024 * gens / t_en
-        out["ga_%s_energy_call_us" % name] = 1e6 * t_en / gens
-        out["ga_%s_generation_ms" % name] = 1e3 * wall / gens
-        if prec == G.GOAC_MIXED:
-            # the symmetric product forms the upper triangle of the (k, n) plane, hi
-            # and lo: 2 x 2 x P x M (M + 1) / 2 flops per call
-            flops = 2 * 2.0 * 1024 * 2048 * 2049 / 2
-            out["ga_mixed_mfma_frac"] = flops / (t_en / gens) / BF16_PEAK
-            out["ga_run_mixed_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, prec, 1024, gens)
-    out["energies_per_s"] = out["ga_mixed_energies_per_s"]
+    pop = pb.init_occupations(1024, seed=0)
+    out["ga_mixed_tile_autotuned"] = pb.energies_autotune(pop)
+    out["ga_mixed_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, G.GOAC_MIXED, 1024, generations)
+    out["ga_fp64_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, G.GOAC_FP64, 1024, max(10, generations // 10))
     pb.close()
-    # the same generation loop on the 4x4x4 cell (M = 256), where a generation is short
-    # enough for the per-call work to show: generation by generation from Python
-    # against goac_ga_run (graph replays)
     cell = S.config2()
     V = ctx.build_ewald(cell["lattice"], cell["pos"])
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
@@ -259,6 +372,9 @@ def ga_energies(ctx, G, S, torch, stream, generations):
     out["ga_cfg2_loop_generation_ms"] = 1e3 * (time.perf_counter() - t0) / gens
     out["ga_cfg2_run_generation_ms"] = 1e3 * ga_run_time(G, pb, torch, G.GOAC_MIXED, 1024, gens)
     pb.close()
+    print("  [ga] cfg3 %.3f ms (mixed), %.3f ms (fp64) per generation" % (out["ga_mixed_generation_ms"],
+                                                                         out["ga_fp64_generation_ms"]),
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -275,53 +391,13 @@ def ga_run_time(G, pb, torch, prec, P, gens):
     return (time.perf_counter() - t0) / gens
 
 
-def large_cell(ctx, G, S, torch, stream):
-    """16x16x8 rock-salt (N = 16384, M = 8192): 8192 chains x 1e5 trials, kT 0.5 ->
-    0.01 eV over 100 blocks; mixed (FP32 field, batched FP64 anchors) against plain
-    FP64. The field updates stream two rows of V_mm per update: HBM roofline."""
-    cell = S.config5()
-    V = ctx.build_ewald(cell["lattice"], cell["pos"])
-    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
-    del V
-    torch.cuda.empty_cache()
-    C, T, M = 8192, 100000, 8192
-    occ0 = pb.init_occupations(C, seed=0)
-    kT = np.geomspace(0.5, 0.01, 100)
-    out = {}
-    for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
-        ch = G.Chains(pb, occ0, prec)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        ch.sweep(T, kT, T // 100, seed=0, reanchor_every=1024)
-        b.record(stream)
-        torch.cuda.synchronize()
-        sec = a.elapsed_time(b) * 1e-3
-        _, _, st = ch.export()
-        upd = float(st["updates"].sum())
-        row_bytes = upd * 2 * M * (4 if prec == G.GOAC_MIXED else 8)
-        out["cfg5_%s_trials_per_s" % name] = C * T / sec
-        out["cfg5_%s_sweep_s" % name] = sec
-        out["cfg5_%s_field_update_GBs" % name] = row_bytes / sec / 1e9
-        out["cfg5_%s_field_update_hbm_frac" % name] = row_bytes / sec / 1e9 / HBM_PEAK_GBS
-        if prec == G.GOAC_MIXED:
-            out["cfg5_accept_rate"] = float(st["accepts"].sum()) / (C * T)
-            out["cfg5_field_updates_per_chain"] = upd / C
-            out["cfg5_fallbacks_per_chain"] = float(st["fallbacks"].sum()) / C
-            out["cfg5_anchors_per_chain"] = float(st["anchors"].sum()) / C
-        ch.close()
-        print("  [cfg5 %s] %.3f s" % (name, sec), file=sys.stderr, flush=True)
-    out["cfg5_mixed_vs_fp64"] = out["cfg5_mixed_trials_per_s"] / out["cfg5_fp64_trials_per_s"]
-    pb.close()
-    return out
-
-
 def batched_instances(ctx, G, S, torch, stream):
     """512 rock-salt/spinel instances (N log-uniform in [64, 2048]), 256 chains each,
-    2e4 trials, kT 0.3 -> 0.01 eV over 20 blocks, one persistent launch whose
-    workgroup size and chains per compute unit the autotuner picks (on a 2000-trial
-    probe that leaves the chains unchanged, not timed)."""
+    2e4 trials, kT 0.3 -> 0.01 eV over 20 blocks. Mixed+batched: one persistent
+    launch of every chain, workgroup size and chains per compute unit from the
+    autotuner (on a 2000-trial probe that leaves the chains unchanged, not timed).
+    Batched FP64: the same launch with the FP64 field. Plain FP64: one chain set and
+    one launch per instance with the size rule's configuration, no autotuning."""
     cells = S.config4()
     t0 = time.perf_counter()
     pbs = []
@@ -333,23 +409,34 @@ def batched_instances(ctx, G, S, torch, stream):
     t_setup = time.perf_counter() - t0
     flat = torch.cat(occs)
     kT = np.geomspace(0.3, 0.01, 20)
+    total = 512 * 256 * 20000
     out = {}
     for prec, name in ((G.GOAC_MIXED, "mixed"), (G.GOAC_FP64, "fp64")):
         ch = G.Chains.batch(pbs, [256] * len(pbs), flat, prec)
         out["cfg4_%s_autotune" % name] = list(ch.autotune(2000, 0.3))
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        ch.sweep(20000, kT, 1000, seed=0, reanchor_every=1024)
-        b.record(stream)
-        torch.cuda.synchronize()
-        sec = a.elapsed_time(b) * 1e-3
-        out["cfg4_%s_trials_per_s" % name] = 512 * 256 * 20000 / sec
+        ch.sweep(20000, kT, 1000, seed=0, reanchor_every=1024, timing=True)
+        sec = ch.timing()[0]
+        out["cfg4_%s_trials_per_s" % name] = total / sec
         out["cfg4_%s_sweep_s" % name] = sec
         ch.close()
         print("  [cfg4 %s] %.3f s" % (name, sec), file=sys.stderr, flush=True)
+    # plain FP64: per-instance chain sets and launches (events around all of them)
+    sets = [G.Chains(pb, occs[i].view(256, -1), G.GOAC_FP64, instance=i) for i, pb in enumerate(pbs)]
+    a, b = ev(torch), ev(torch)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for ch in sets:
+        ch.sweep(20000, kT, 1000, seed=0, reanchor_every=1024)
+    b.record(stream)
+    b.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    for ch in sets:
+        ch.close()
+    out["cfg4_plain_fp64_trials_per_s"] = total / sec
+    out["cfg4_plain_fp64_sweep_s"] = sec
+    out["cfg4_mixed_vs_plain_fp64"] = out["cfg4_mixed_trials_per_s"] / out["cfg4_plain_fp64_trials_per_s"]
     out["cfg4_setup_s"] = t_setup
+    print("  [cfg4 plain fp64] %.3f s" % sec, file=sys.stderr, flush=True)
     for pb in pbs:
         pb.close()
     return out
@@ -555,21 +642,23 @@ def hybrid(ctx, G, S, torch, stream):
             "hybrid_best_E_per_round": best}
 
 
-def cpu_baseline(S):
-    """The FP64 oracle (unchanged) on the host cores: one full step of the same
-    workload (Ewald matrix, 4096 chains x 1e5 trials, energies of the bests, a
-    GA generation, top-64), OpenMP over rows, chains and configurations."""
+def cpu_baseline(S, kT):
+    """The FP64 oracle (unchanged) on the host cores, on a bounded sample of the
+    step: 64 of its 8192 chains with the full 1e5 trials and the same temperature
+    schedule, OpenMP over chains. The oracle's own pair matrix of the cell (from one
+    row relabelled by translation) is built first and timed apart; the rate counts
+    the Monte Carlo alone and is the per-trial rate of the whole step's sweep."""
     import oracle as O
-    cell = S.config2()
+    cell = S.config5()
     nthreads = O.num_threads()
     t0 = time.perf_counter()
-    V = O.cell_matrix(cell)
-    occ0 = O.init_occupations(cell, CHAINS, seed=0)
+    V = O.grid_matrix(cell)
+    t_v = time.perf_counter() - t0
+    C = 64
+    occ0 = O.init_occupations(cell, C, seed=0)
     st = O.MCState(occ0)
-    O.mc_run(V, cell, st, seed=0, n_trials=TRIALS, kT=np.geomspace(0.5, 0.01, BLOCKS), block_len=BLOCK_LEN)
-    E = O.energies(V, st.best_occ, cell["charge"])
-    O.ga_generation(cell, st.best_occ, E, seed=0, g=0, n_elite=8, p_mut=0.2)
-    O.topk(V, st.best_occ, cell["charge"], 64)
+    t0 = time.perf_counter()
+    O.mc_run(V, cell, st, seed=0, n_trials=T5, kT=kT, block_len=BLOCK_LEN)
     dt = time.perf_counter() - t0
     model = ""
     try:
@@ -579,9 +668,10 @@ def cpu_baseline(S):
                 break
     except OSError:
         pass
-    return {"value": CHAINS * TRIALS / dt, "unit": "swap-trials/s", "cores": nthreads, "kind": "oracle",
-            "sample": "one full step of the workload (4096 chains x 1e5 trials plus Ewald, energies, GA, "
-                      "top-64) in %.1f s" % dt, "cpu": model}
+    return {"value": C * T5 / dt, "unit": "swap-trials/s", "cores": nthreads, "kind": "oracle",
+            "sample": "64 of the step's 8192 chains x 1e5 trials (same schedule) in %.1f s, extrapolated per trial; "
+                      "the oracle's pair matrix of the cell took %.1f s more, not counted" % (dt, t_v),
+            "cpu": model}
 
 
 if __name__ == "__main__":

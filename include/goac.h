@@ -236,6 +236,7 @@ goac_status goac_chains_create_batch(goac_problem* const* pbs, int32_t n_instanc
 
 #define GOAC_MC_TRACE_HASH 1u   /* accumulate the per-trial trajectory hash */
 #define GOAC_REMC_GRAPH 2u      /* goac_remc_run: replay rounds from a captured HIP graph */
+#define GOAC_MC_TIMING 4u       /* goac_mc_sweep: HIP events around each launch (goac_chains_timing) */
 
 /* Parameters of one sweep. kT_host is a table of n_rows x n_blocks kT values
  * (eV); chain c at trial t uses row r_c (the chain set's temperature row, 0
@@ -297,6 +298,14 @@ typedef struct {
  *                        (may be NULL) */
 goac_status goac_chains_autotune(goac_chains* ch, uint64_t probe_trials, double kT, int32_t* wg_out,
                                  int32_t* per_cu_out);
+
+/* Device time of the sweeps run with GOAC_MC_TIMING since the last call: the sum
+ * over the Monte Carlo kernel launches and the sum over the batched FP64 anchors
+ * between sweep chunks (cells of more than 1024 mobile positions, GOAC_MIXED),
+ * from HIP events recorded on the context's stream around each, and the number of
+ * Monte Carlo launches. Synchronises; resets the sums. Any pointer may be NULL. */
+goac_status goac_chains_timing(goac_chains* ch, double* mc_seconds, double* anchor_seconds,
+                               int64_t* mc_launches);
 
 /* Copy chain results to caller buffers (any pointer may be NULL):
  *   occ_dev, best_occ_dev : C x n; stats_dev : C goac_chain_stats (device).

@@ -23,6 +23,7 @@ GOAC_FP64, GOAC_MIXED = 0, 1
 EDRIFT = -6
 TRACE_HASH = 1
 REMC_GRAPH = 2
+MC_TIMING = 4
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTNEUTRAL", -5: "EINEXACT",
            -6: "EDRIFT", -7: "ESTATE"}
@@ -74,7 +75,7 @@ EXPORTED = ["goac_ctx_create", "goac_ctx_destroy", "goac_last_error", "goac_ctx_
             "goac_chains_create_batch", "goac_chains_set_rows", "goac_mc_sweep", "goac_chains_export",
             "goac_remc_exchange", "goac_ga_generation", "goac_gd_run", "goac_chains_load",
             "goac_hybrid_round", "goac_chains_autotune", "goac_remc_run", "goac_ga_run", "goac_energies_tile",
-            "goac_energies_autotune", "goac_energies_noalloc"]
+            "goac_energies_autotune", "goac_energies_noalloc", "goac_chains_timing"]
 
 
 def load():
@@ -105,6 +106,7 @@ def load():
         "goac_chains_set_rows": ([P, P], I32),
         "goac_mc_sweep": ([P, P], I32),
         "goac_chains_export": ([P, P, P, P], I32),
+        "goac_chains_timing": ([P, P, P, P], I32),
         "goac_remc_exchange": ([P, I32, P, U64, U64, P, P], I32),
         "goac_ga_generation": ([P, I64, P, P, P, P], I32),
         "goac_ga_run": ([P, I64, P, P, P, I32, I32], I32),
@@ -336,24 +338,33 @@ class Chains:
         r = _np(rows, np.int32)
         self.ctx.check(load().goac_chains_set_rows(self._h, r.ctypes.data_as(C.c_void_p)))
 
-    def sweep(self, n_trials, kT, block_len=None, seed=0, reanchor_every=1024, trace=False, variant=0):
+    def sweep(self, n_trials, kT, block_len=None, seed=0, reanchor_every=1024, trace=False, variant=0,
+              timing=False):
         kT = _np(np.atleast_2d(kT), np.float64)
         rows, nb = kT.shape
         if block_len is None:
             block_len = max(1, int(n_trials))
         prm = MCParams(seed, n_trials, kT.ctypes.data_as(C.c_void_p), rows, nb, block_len, reanchor_every,
-                       TRACE_HASH if trace else 0, variant, 0)
+                       (TRACE_HASH if trace else 0) | (MC_TIMING if timing else 0), variant, 0)
         self._kT = kT  # the library copies the table before returning; kept for clarity
         self.ctx.check(load().goac_mc_sweep(self._h, C.byref(prm)))
 
-    def export(self, host_stats=True, drift_ok=False):
+    def timing(self):
+        """(Monte Carlo launch seconds, batched anchor seconds, Monte Carlo launches)
+        of the sweeps run with timing=True since the last call (waits for them)."""
+        mc, an, n = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
+        self.ctx.check(load().goac_chains_timing(self._h, C.byref(mc), C.byref(an), C.byref(n)))
+        return mc.value, an.value, n.value
+
+    def export(self, host_stats=True, drift_ok=False, occ=True):
         """(occupations, best occupations, stats) with stats a numpy structured array,
         or, with host_stats=False, the raw uint8 device tensor. The library call
         waits for the copies and raises EDRIFT when a chain's FP32 field has left its
         error bound, unless drift_ok (the copies are made either way; the chains'
-        status field says which)."""
+        status field says which). occ=False skips the current occupations (None)."""
         tot = sum(c * n for c, n in self._n_per)
-        occ = torch.empty(tot, dtype=torch.uint8, device=self.ctx.device)
+        want_occ = occ
+        occ = torch.empty(tot, dtype=torch.uint8, device=self.ctx.device) if want_occ else None
         best = torch.empty(tot, dtype=torch.uint8, device=self.ctx.device)
         st = torch.empty(self.C * STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.ctx.device)
         rc = load().goac_chains_export(self._h, _ptr(occ), _ptr(best), _ptr(st))
@@ -366,7 +377,7 @@ class Chains:
             stats = st
         if len(self._n_per) == 1:
             c, n = self._n_per[0]
-            occ, best = occ.view(c, n), best.view(c, n)
+            occ, best = (occ.view(c, n) if occ is not None else None), best.view(c, n)
         return occ, best, stats
 
     def remc_exchange(self, R, kT_ladder, x, seed, slot, acc=None):

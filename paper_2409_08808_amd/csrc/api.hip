@@ -768,7 +768,8 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     ArenaPlan ap;
     const size_t o_mob = ap.take(M * 4), o_msub = ap.take(Mp), o_ref = ap.take(n), o_chg = ap.take(E * 8),
                  o_dq = ap.take(S * E * 8), o_tab = ap.take(tab.size() * 4), o_spos = ap.take(M * 4),
-                 o_sinv = ap.take(M * 4), o_fix = ap.take((nf + 1) * 4), o_fq = ap.take((nf + 1) * 8),
+                 o_sinv = ap.take(M * 4), o_site = ap.take(M * 4), o_fix = ap.take((nf + 1) * 4),
+                 o_fq = ap.take((nf + 1) * 8),
                  o_c = ap.take(Mp * 8), o_q = ap.take(Mp * 8);
     const size_t up_end = ap.end;
     const size_t o_V64 = ap.take((size_t)M * Mp * 8), o_V32 = ap.take((size_t)M * Mp * 4),
@@ -790,6 +791,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     d.tab = (int32_t*)(base + o_tab);
     pb->spos = (int32_t*)(base + o_spos);
     pb->spos_inv = (int32_t*)(base + o_sinv);
+    pb->ssite = (int32_t*)(base + o_site);
     pb->fixed_idx = (int32_t*)(base + o_fix);
     double* w_fq = (double*)(base + o_fq);
     double* w_c = (double*)(base + o_c);
@@ -817,6 +819,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     std::memcpy(img.data() + o_tab, tab.data(), tab.size() * 4);
     std::memcpy(img.data() + o_spos, spos.data(), M * 4);
     std::memcpy(img.data() + o_sinv, spos_inv.data(), M * 4);
+    for (int32_t x = 0; x < M; ++x) reinterpret_cast<int32_t*>(img.data() + o_site)[x] = mob[spos[x]];
     if (nf) std::memcpy(img.data() + o_fix, fixed.data(), nf * 4);
     if (nf) std::memcpy(img.data() + o_fq, fq.data(), nf * 8);
     std::memcpy(img.data() + o_c, cvec.data(), Mp * 8);
@@ -1264,6 +1267,8 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
 }
 
 static void chains_free(goac_chains* ch) {
+    for (hipEvent_t e : ch->tev) (void)hipEventDestroy(e);
+    ch->tev.clear();
     if (ch->arena) pool_put(ch->ctx, ch->arena, ch->arena_bytes);
     ch->arena = nullptr;
     pool_put(ch->ctx, ch->kT, ch->kT_cap * 8);
@@ -1471,23 +1476,44 @@ static goac_status sweep_upload_kT(goac_chains* ch, const double* kT_host, size_
 // record them. The persistent grid pulls chains from a counter reset before each
 // launch.
 // zero_queue false: the caller has cleared the work counter (one launch only)
+// a timing mark: records the next event of a pair (GOAC_MC_TIMING)
+static goac_status timing_mark(goac_chains* ch, uint8_t kind) {
+    goac_ctx* ctx = ch->ctx;
+    if (ch->tev_used == ch->tev.size()) {
+        hipEvent_t e = nullptr;
+        GOAC_HIP(ctx, hipEventCreate(&e));
+        ch->tev.push_back(e);
+        ch->tev_kind.push_back(kind);
+    }
+    ch->tev_kind[ch->tev_used] = kind;
+    GOAC_HIP(ctx, hipEventRecord(ch->tev[ch->tev_used++], ctx->stream));
+    return GOAC_OK;
+}
+
 static goac_status sweep_enqueue(goac_chains* ch, SweepPlan P, bool trace, uint64_t n_trials,
-                                 int32_t reanchor_every, bool zero_queue = true) {
+                                 int32_t reanchor_every, bool zero_queue = true, bool timing = false) {
     goac_ctx* ctx = ch->ctx;
     const bool mixed = ch->prec == GOAC_MIXED;
     P.a.kT = ch->kT;
     if (P.a.inline_anchor) {
         P.a.n_trials = n_trials;
         if (zero_queue) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
-        return mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid);
+        if (timing) GOAC_TRY(timing_mark(ch, 0));
+        GOAC_TRY(mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid));
+        if (timing) GOAC_TRY(timing_mark(ch, 0));
+        return GOAC_OK;
     }
     const uint64_t chunk = (uint64_t)reanchor_every * 8;
     for (uint64_t done = 0; done < n_trials; done += chunk) {
         P.a.n_trials = std::min<uint64_t>(chunk, n_trials - done);
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ch->queue, 1);
+        if (timing) GOAC_TRY(timing_mark(ch, 0));
         GOAC_TRY(mc_launch(ctx, P.a, mixed, trace, P.wg, P.lds, P.grid));
+        if (timing) GOAC_TRY(timing_mark(ch, 0));
+        if (timing) GOAC_TRY(timing_mark(ch, 1));
         for (size_t i = 0; i < ch->pbs.size(); ++i)
             GOAC_TRY(anchor_batched(ctx, ch, (int)i, (uint32_t)reanchor_every));
+        if (timing) GOAC_TRY(timing_mark(ch, 1));
     }
     return GOAC_OK;
 }
@@ -1519,7 +1545,29 @@ extern "C" goac_status goac_mc_sweep(goac_chains* ch, const goac_mc_params* prm)
     const int wg = prm->variant != 0 ? prm->variant : ch->tuned_wg;
     const int per_cu = prm->variant != 0 ? 0 : ch->tuned_per_cu;
     GOAC_TRY(sweep_plan(ch, prm, wg, per_cu, &P));
-    return sweep_enqueue(ch, P, (prm->flags & GOAC_MC_TRACE_HASH) != 0, prm->n_trials, prm->reanchor_every);
+    return sweep_enqueue(ch, P, (prm->flags & GOAC_MC_TRACE_HASH) != 0, prm->n_trials, prm->reanchor_every, true,
+                         (prm->flags & GOAC_MC_TIMING) != 0);
+}
+
+extern "C" goac_status goac_chains_timing(goac_chains* ch, double* mc_seconds, double* anchor_seconds,
+                                          int64_t* mc_launches) {
+    if (!ch) return GOAC_EINVAL;
+    goac_ctx* ctx = ch->ctx;
+    GOAC_HIP(ctx, hipSetDevice(ctx->device));
+    double t[2] = {0.0, 0.0};
+    int64_t launches = 0;
+    if (ch->tev_used > 0) GOAC_HIP(ctx, hipEventSynchronize(ch->tev[ch->tev_used - 1]));
+    for (size_t e = 0; e + 1 < ch->tev_used; e += 2) {
+        float ms = 0.0f;
+        GOAC_HIP(ctx, hipEventElapsedTime(&ms, ch->tev[e], ch->tev[e + 1]));
+        t[ch->tev_kind[e]] += 1e-3 * (double)ms;
+        if (ch->tev_kind[e] == 0) ++launches;
+    }
+    ch->tev_used = 0;
+    if (mc_seconds) *mc_seconds = t[0];
+    if (anchor_seconds) *anchor_seconds = t[1];
+    if (mc_launches) *mc_launches = launches;
+    return GOAC_OK;
 }
 
 // ------------------------------------------------------------------ autotuning

@@ -227,6 +227,7 @@ struct goac_problem {
     std::vector<double> shift_host;  // c_s
     int32_t* spos = nullptr;         // M: positions of each sublattice, ascending, concatenated
     int32_t* spos_inv = nullptr;     // M: index of position k in spos
+    int32_t* ssite = nullptr;        // M: site of entry x of spos (mob[spos[x]])
     int32_t* fixed_idx = nullptr;    // fixed sites
     int32_t n_fixed = 0;
     mutable bool e_host = false;     // E_ff, E_t read back (on the first request)
@@ -275,6 +276,11 @@ struct goac_chains {
     double* ladder = nullptr;         // replica-exchange ladder (device) and its host copy
     size_t ladder_cap = 0;
     std::vector<double> ladder_last;
+    // GOAC_MC_TIMING: event pairs recorded around each Monte Carlo launch (kind 0)
+    // and each batched anchor (kind 1) since the timings were last read
+    std::vector<hipEvent_t> tev;
+    std::vector<uint8_t> tev_kind;
+    size_t tev_used = 0;
 };
 
 // ------------------------------------------------------------------ error helpers

@@ -1,6 +1,8 @@
 // Genetic-algorithm generation, random starts and top-k selection on gfx950
 // (SI, "Genetic Algorithm" and "Random"; Methodology: output of the n lowest
 // configurations).
+#include <algorithm>
+
 #include "common.h"
 
 namespace goac {
@@ -141,159 +143,140 @@ __device__ inline int wave_find(int from, int len, Pred pred) {
     return len;
 }
 
-// Crossover walk of one sublattice held in registers (len <= 4096 positions,
-// species ids < kRegSpecies). Lane l owns positions 64 l .. 64 l + 63: the bytes of
-// ref (the path copy), of parent B and of the child in R, Bv, Cv (dword d holds
-// positions 4 d .. 4 d + 3), one 64-bit word of each species' bit row (bit j: the
-// position holds e in ref and disagrees with B), the word of disagreeing positions
-// still to visit (mm), and, in lane e, the head of species e's row. A step reads
-// and writes single bytes and words of given lanes with uniform register indices
-// (no memory traffic); the coin bits of a chunk are drawn when the walk enters
-// it. Returns false on a species id out of range or a broken composition.
-constexpr int kRegSpecies = 16;
-constexpr int kRegMaxLen = 64 * 64;
 // sublattices up to this length take the byte walk (crossover_bytes), longer ones
-// the register walk when it applies, else the scan walk
+// the row walk (crossover_rows) when its rows fit in LDS, else the scan walk
 constexpr int kByteMaxLen = 1024;
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
 
-__device__ bool crossover_regs(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s,
-                               uint64_t* mk, uint32_t c, uint32_t g, uint64_t seed, int lane) {
-    uint32_t R[16], Bv[16], Cv[16];
-    const int x0 = lane * 64;
-#pragma unroll
-    for (int d = 0; d < 16; ++d) {
-        uint32_t r = 0, b = 0, ch = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * d + k;
-            if (x < len) {
-                r |= (uint32_t)rs[x] << (8 * k);
-                b |= (uint32_t)bs[x] << (8 * k);
-                ch |= (uint32_t)cs[x] << (8 * k);
-            }
-        }
-        R[d] = r;
-        Bv[d] = b;
-        Cv[d] = ch;
-    }
-    // species rows through LDS: lane l ors bit j into mk[e][l] for each of its
-    // disagreeing positions (each lane touches only its own column)
-    for (int e = 0; e < kRegSpecies; ++e) mk[e * 64 + lane] = 0;
-    wave_lds_order();
-    uint64_t mm = 0;
-    bool ok = true;
-#pragma unroll
-    for (int d = 0; d < 16; ++d)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t e = byte_of(R[d], k), b = byte_of(Bv[d], k);
-            if (e != b) {
-                if (e < kRegSpecies && b < kRegSpecies) {
-                    const uint64_t bit = 1ull << (4 * d + k);
-                    atomicOr(reinterpret_cast<unsigned long long*>(&mk[e * 64 + lane]), (unsigned long long)bit);
-                    mm |= bit;
-                } else {
-                    ok = false;
-                }
-            }
-        }
-    if (__ballot(!ok)) return false;
-    wave_lds_order();
-    uint64_t rows[kRegSpecies];
-#pragma unroll
-    for (int e = 0; e < kRegSpecies; ++e) rows[e] = mk[e * 64 + lane];
-    int hv = kInf;
-#pragma unroll
-    for (int e = 0; e < kRegSpecies; ++e) {
-        const uint64_t m = __ballot(rows[e] != 0);
-        if (m) {
-            const int l = (int)__ffsll((long long)m) - 1;
-            const uint64_t v = readlane64(rows[e], l);
-            if (lane == e) hv = l * 64 + (int)__ffsll((long long)v) - 1;
-        }
-    }
+// Crossover walk of a sublattice with bit rows in LDS, one 64-bit word per 64
+// positions (nw words each): dis, the positions of the path copy ref that differ
+// from B; coin, the coin bit of every differing position (all drawn up front, 64
+// positions per ballot); and for each species e, hold[e], the positions holding e
+// in ref and differing from B. Every position before the walk's p agrees with B
+// in ref, so p's partner q is the first position of hold[B[p]].
+// The walk keeps its current window of 64 positions in registers: lane l holds
+// ref, B and the child at position 64 w + l, and lane e the window's word of
+// hold[e]. A step whose partner lies in the window reads and writes only those
+// registers (readlane / writelane with uniform indices); a partner further on is
+// found with 64-word ballots over LDS, where its updates go too. Leaving a window
+// writes its child bytes back (its ref and rows are no longer needed: every
+// position of it then agrees with B).
+__device__ __forceinline__ uint32_t lane_get(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+__device__ void crossover_rows(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s, int E,
+                               uint64_t* rows, uint32_t c, uint32_t g, uint64_t seed, int lane) {
     const int nw = (len + 63) >> 6;
+    uint64_t* dis = rows;
+    uint64_t* coin = rows + nw;
+    uint64_t* hold = rows + 2 * nw;
+    for (int x = lane; x < E * nw; x += 64) hold[x] = 0;
+    wave_lds_order();
     for (int w = 0; w < nw; ++w) {
-        uint64_t cur = readlane64(mm, w);
-        if (!cur) continue;
-        // coins of the chunk: lane j draws position 64 w + j
-        const int xj = w * 64 + lane;
-        const bool coin = xj < len && (philox((uint32_t)spos_s[xj], c, g, TAG_X, seed).x >> 31) != 0;
-        const uint64_t xm = __ballot(coin);
-        while (cur) {
-            const int po = (int)__ffsll((long long)cur) - 1;
-            cur &= cur - 1;
-            const int p = w * 64 + po;
-            const int a = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)R[po >> 2], w), po & 3);
-            const int b = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)Bv[po >> 2], w), po & 3);
-            const int q = __builtin_amdgcn_readlane(hv, b);
-            if (q >= len || q <= p) return false;
-            const int qw = q >> 6, qo = q & 63;
-            const int bq = (int)byte_of((uint32_t)__builtin_amdgcn_readlane((int)Bv[qo >> 2], qw), qo & 3);
-            const bool carry = bq != a;   // q keeps disagreeing with B after taking a
-            const uint64_t bitq = 1ull << qo, bitp = 1ull << po;
-            // row of b loses q; its new head is the first set bit from lane qw on
-            uint64_t rb = rows[b];
-            rb = lane == qw ? rb & ~bitq : rb;
-            rows[b] = rb;
-            int hb = kInf;
-            {
-                const uint64_t m = __ballot(lane >= qw && rb != 0);
-                if (m) {
-                    const int l = (int)__ffsll((long long)m) - 1;
-                    hb = l * 64 + (int)__ffsll((long long)readlane64(rb, l)) - 1;
-                }
-            }
-            // row of a loses p and gains q when q keeps disagreeing
-            uint64_t ra = rows[a];
-            ra = lane == w ? ra & ~bitp : ra;
-            if (carry) ra = lane == qw ? ra | bitq : ra;
-            rows[a] = ra;
-            int ha = kInf;
-            {
-                const uint64_t m = __ballot(lane >= w && ra != 0);
-                if (m) {
-                    const int l = (int)__ffsll((long long)m) - 1;
-                    ha = l * 64 + (int)__ffsll((long long)readlane64(ra, l)) - 1;
-                }
-            }
-            hv = lane == b ? hb : hv;
-            hv = lane == a ? ha : hv;
-            // ref[q] = a
-            {
-                const uint32_t sh = 8u * (uint32_t)(qo & 3);
-                const uint32_t v = R[qo >> 2];
-                const uint32_t nv = (v & ~(0xffu << sh)) | ((uint32_t)a << sh);
-                R[qo >> 2] = lane == qw ? nv : v;
-            }
-            if (!carry) {
-                if (qw == w) cur &= ~bitq;
-                else mm = lane == qw ? mm & ~bitq : mm;
-            }
-            // the child takes this swap of the path with probability 1/2
-            if ((xm >> po) & 1) {
-                const uint32_t vp = Cv[po >> 2], vq = Cv[qo >> 2];
-                const uint32_t cp = byte_of((uint32_t)__builtin_amdgcn_readlane((int)vp, w), po & 3);
-                const uint32_t cq = byte_of((uint32_t)__builtin_amdgcn_readlane((int)vq, qw), qo & 3);
-                const uint32_t shp = 8u * (uint32_t)(po & 3), shq = 8u * (uint32_t)(qo & 3);
-                Cv[po >> 2] = lane == w ? (vp & ~(0xffu << shp)) | (cq << shp) : vp;
-                const uint32_t vq2 = Cv[qo >> 2];
-                Cv[qo >> 2] = lane == qw ? (vq2 & ~(0xffu << shq)) | (cp << shq) : vq2;
-            }
+        const int x = w * 64 + lane;
+        const bool in = x < len;
+        const int a = in ? rs[x] : 0;
+        const bool d = in && a != bs[x];
+        const uint32_t sp = in ? (uint32_t)spos_s[x] : 0u;
+        const bool cn = d && (philox(sp, c, g, TAG_X, seed).x >> 31) != 0;
+        const uint64_t dm = __ballot(d), cm = __ballot(cn);
+        if (d) atomicOr(reinterpret_cast<unsigned long long*>(&hold[a * nw + w]), 1ull << lane);
+        if (lane == 0) {
+            dis[w] = dm;
+            coin[w] = cm;
         }
     }
-    // child bytes back to LDS
-#pragma unroll
-    for (int d = 0; d < 16; ++d)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * d + k;
-            if (x < len) cs[x] = (uint8_t)byte_of(Cv[d], k);
-        }
     wave_lds_order();
-    return true;
+    int w = -1;
+    uint64_t cur = 0, cw = 0;
+    uint32_t rv = 0, bv = 0, cv = 0;   // the window: ref, B and the child at 64 w + lane
+    uint64_t hw = 0;                   // lane e: the window's word of hold[e]
+    for (;;) {
+        if (!cur) {
+            // leave the window (child bytes back to LDS), then find the next word
+            // with a differing position and load its window
+            if (w >= 0 && w * 64 + lane < len) cs[w * 64 + lane] = (uint8_t)cv;
+            int nxt = nw;
+            for (int base = w + 1; base < nw; base += 64) {
+                const int y = base + lane;
+                const uint64_t m = __ballot(y < nw && dis[y] != 0);
+                if (m) {
+                    nxt = base + (int)__ffsll((long long)m) - 1;
+                    break;
+                }
+            }
+            wave_lds_order();
+            if (nxt >= nw) break;
+            w = nxt;
+            const int x = w * 64 + lane;
+            const bool in = x < len;
+            rv = in ? rs[x] : 0u;
+            bv = in ? bs[x] : 0u;
+            cv = in ? cs[x] : 0u;
+            hw = lane < E ? hold[lane * nw + w] : 0ull;
+            cur = dis[w];
+            cw = coin[w];
+            wave_lds_order();
+        }
+        const int po = (int)__ffsll((long long)cur) - 1;
+        cur &= cur - 1;
+        const int a = (int)lane_get(rv, po);
+        const int b = (int)lane_get(bv, po);
+        const uint32_t cp = lane_get(cv, po);
+        const bool take = (cw >> po) & 1ull;   // the child takes this swap of the path
+        const uint64_t bitp = 1ull << po;
+        // partner: the first holder of b, in the window or further on
+        const uint64_t hv = readlane64(hw, b);
+        // p now agrees: it leaves hold[a]
+        hw = lane == a ? hw & ~bitp : hw;
+        if (hv) {
+            // in the window: registers only, no branches
+            const int qo = (int)__ffsll((long long)hv) - 1;
+            const uint64_t bitq = 1ull << qo;
+            const int bq = (int)lane_get(bv, qo);
+            const uint32_t cq = lane_get(cv, qo);
+            const bool carry = bq != a;   // q keeps differing from B after taking a
+            hw = lane == b ? hw & ~bitq : hw;
+            hw = (carry && lane == a) ? hw | bitq : hw;
+            rv = (carry && lane == qo) ? (uint32_t)a : rv;
+            cur = carry ? cur : cur & ~bitq;
+            cv = (take && lane == po) ? cq : ((take && lane == qo) ? cp : cv);
+        } else {
+            int qw = nw;
+            uint64_t hq = 0;
+            const uint64_t* hb = hold + b * nw;
+            for (int base = w + 1; base < nw; base += 64) {
+                const int y = base + lane;
+                const uint64_t v = y < nw ? hb[y] : 0ull;
+                const uint64_t m = __ballot(v != 0);
+                if (m) {
+                    const int l = (int)__ffsll((long long)m) - 1;
+                    qw = base + l;
+                    hq = readlane64(v, l);
+                    break;
+                }
+            }
+            if (qw >= nw) break;   // cannot happen: ref and B share the composition
+            const int qo = (int)__ffsll((long long)hq) - 1;
+            const int q = qw * 64 + qo;
+            const int bq = bs[q];
+            const uint8_t cq = cs[q];
+            const bool carry = bq != a;
+            if (lane == 0) {
+                hold[b * nw + qw] = hq & ~(1ull << qo);
+                rs[q] = (uint8_t)a;
+                if (carry) atomicOr(reinterpret_cast<unsigned long long*>(&hold[a * nw + qw]), 1ull << qo);
+                else atomicAnd(reinterpret_cast<unsigned long long*>(&dis[qw]), ~(1ull << qo));
+                if (take) cs[q] = (uint8_t)cp;
+            }
+            cv = (take && lane == po) ? (uint32_t)cq : cv;
+            wave_lds_order();
+        }
+    }
+    if (w >= 0 && w * 64 + lane < len) cs[w * 64 + lane] = (uint8_t)cv;   // (already written on the normal exit)
+    wave_lds_order();
 }
 
 // Crossover walk of one sublattice of at most 256 NR positions held in registers,
@@ -384,18 +367,17 @@ __device__ void crossover_bytes(uint8_t* cs, const uint8_t* bs, int len, const i
 //     each swap of the path iff the top bit of Philox(p_mobile, c, g, X) is set.
 //   mutation: with probability p_mut one valid swap, drawn as an MC proposal
 //     with the sublattice's positions ordered by (species, position).
-// Sublattices of up to 1024 positions take the byte walk (crossover_bytes); those
-// of 1025..4096 positions with at most 16 species the species-row walk
-// (crossover_regs, compiled in only when REG); others the scan walk, which finds p
-// and q with 64-position ballots over the path copy in LDS.
-template <bool REG>
+// Sublattices of up to 1024 positions take the byte walk (crossover_bytes); longer
+// ones the row walk (crossover_rows) when rows_words > 0 (the LDS of its rows, in
+// 64-bit words), else the scan walk, which finds p and q with 64-position ballots
+// over the path copy in LDS.
 __global__ __launch_bounds__(64) void k_ga_child(
     int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
-    const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ mob,
+    const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ ssite,
     const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ, int64_t P,
     const uint8_t* __restrict__ pop_in, const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite,
     int32_t n_elite, uint64_t seed, uint32_t g, const uint32_t* __restrict__ g_dev, double p_mut,
-    uint8_t* __restrict__ pop_out) {
+    int32_t rows_words, uint8_t* __restrict__ pop_out) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int64_t c = blockIdx.x;
     if (g_dev) g += *g_dev;   // a captured generation: the index is base + offset
@@ -425,20 +407,34 @@ __global__ __launch_bounds__(64) void k_ga_child(
         pb = upper_bound_u64(cum, P, mulhi64(xb, W));
     }
     // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent
-    // B); then the register walk's 16 x 64 words of species rows
+    // B); then the row walk's bit rows
     const int Mr = (int)round_up(M, 16);
     uint8_t* ch = lds;
     uint8_t* rf = lds + Mr;
     uint8_t* bb = lds + 2 * Mr;
-    uint64_t* mk = reinterpret_cast<uint64_t*>(lds + round_up(3 * (int64_t)Mr, 16));
+    uint64_t* rows = reinterpret_cast<uint64_t*>(lds + round_up(3 * (int64_t)Mr, 16));
     const uint8_t* A = pop_in + pa * n;
     const uint8_t* B = pop_in + pb * n;
-    for (int x = lane; x < M; x += 64) {
-        const int site = mob[spos[x]];
-        const uint8_t a = A[site];
-        ch[x] = a;
-        rf[x] = a;
-        bb[x] = B[site];
+    // eight positions per lane per round, their loads in flight together
+    for (int x0 = lane; x0 < M; x0 += 8 * 64) {
+        int st[8];
+        uint8_t av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) st[u] = x0 + 64 * u < M ? ssite[x0 + 64 * u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = A[st[u]];
+            bv[u] = B[st[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = x0 + 64 * u;
+            if (x < M) {
+                ch[x] = av[u];
+                rf[x] = av[u];
+                bb[x] = bv[u];
+            }
+        }
     }
     wave_lds_order();
     for (int s = 0; s < S; ++s) {
@@ -452,8 +448,8 @@ __global__ __launch_bounds__(64) void k_ga_child(
             else crossover_bytes<4>(cs, bs, len, spos + base, (uint32_t)c, g, seed, lane);
             continue;
         }
-        if (REG && len <= kRegMaxLen && E <= kRegSpecies) {
-            crossover_regs(rs, cs, bs, len, spos + base, mk, (uint32_t)c, g, seed, lane);
+        if ((int64_t)(E + 2) * ((len + 63) / 64) <= rows_words) {
+            crossover_rows(rs, cs, bs, len, spos + base, E, rows, (uint32_t)c, g, seed, lane);
             continue;
         }
         // scan walk: the next disagreeing position and its partner, 64 positions at a
@@ -512,39 +508,44 @@ __global__ __launch_bounds__(64) void k_ga_child(
             wave_lds_order();
         }
     }
-    for (int x = lane; x < M; x += 64) out[mob[spos[x]]] = ch[x];
+    for (int x0 = lane; x0 < M; x0 += 8 * 64) {
+        int st[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) st[u] = x0 + 64 * u < M ? ssite[x0 + 64 * u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (st[u] >= 0) out[st[u]] = ch[x0 + 64 * u];
+    }
     for (int f = lane; f < n_fixed; f += 64) out[fixed_idx[f]] = ref_occ[fixed_idx[f]];
 }
 
-// The register walk's arrays take most of the register file (one wavefront per
-// SIMD), so its variant runs only for problems with a sublattice it walks.
-static bool ga_reg_walk(const goac_problem* pb) {
-    bool reg = false;
-    for (int s = 0; s < pb->d.S; ++s) {
-        const int len = pb->tab_host[2 + s];
-        reg = reg || (len > kByteMaxLen && len <= kRegMaxLen && pb->d.E <= kRegSpecies);
-    }
-    return reg;
+// LDS of a child: its occupation, the path copy and parent B (bytes), then the row
+// walk's bit rows for the longest sublattice above the byte walk's range: (E + 2)
+// words per 64 positions, left out when they would not fit (those sublattices then
+// take the scan walk)
+static int64_t ga_rows_words(const goac_problem* pb) {
+    int maxlen = 0;
+    for (int s = 0; s < pb->d.S; ++s) maxlen = std::max(maxlen, (int)pb->tab_host[2 + s]);
+    if (maxlen <= kByteMaxLen) return 0;
+    const int64_t words = (int64_t)(pb->d.E + 2) * ((maxlen + 63) / 64);
+    const int64_t base = round_up(3 * round_up(pb->d.M, 16), 16);
+    return base + 8 * words <= 160 * 1024 ? words : 0;
 }
 
-// LDS of a child: its occupation, the path copy and parent B (bytes), then the
-// register walk's 16 x 64 words of species rows
 size_t ga_child_lds(const goac_problem* pb) {
-    return round_up(3 * round_up(pb->d.M, 16), 16) + (ga_reg_walk(pb) ? 8 * kRegSpecies * 64 : 0);
+    return round_up(3 * round_up(pb->d.M, 16), 16) + 8 * ga_rows_words(pb);
 }
 
 goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
                         int32_t n_elite, const goac_ga_params* prm, uint8_t* pop_out, const uint32_t* g_dev) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
-    const bool reg = ga_reg_walk(pb);
     const size_t lds = ga_child_lds(pb);
-    const void* fn = reg ? (const void*)k_ga_child<true> : (const void*)k_ga_child<false>;
-    if (lds > 64 * 1024) GOAC_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    auto launch = reg ? k_ga_child<true> : k_ga_child<false>;
-    hipLaunchKernelGGL(launch, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
-                       pb->spos_inv, d.msub, d.mob, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite,
-                       n_elite, prm->seed, prm->generation, g_dev, prm->p_mut, pop_out);
+    if (lds > 64 * 1024)
+        GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_ga_child, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_ga_child, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
+                       pb->spos_inv, d.msub, pb->ssite, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite,
+                       n_elite, prm->seed, prm->generation, g_dev, prm->p_mut, (int32_t)ga_rows_words(pb), pop_out);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
