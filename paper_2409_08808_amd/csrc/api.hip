@@ -1,6 +1,7 @@
 // C ABI entry points of the gfx950 library (declared in include/goac.h): argument
 // checks, problem derivation, chain-set management and kernel dispatch.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -94,7 +95,11 @@ goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
 
 // ------------------------------------------------------------------ problem derivation kernels
 
-// V64/V32 (M x Mp) and the bf16 split (Mp x Mp) of the mobile block, zero-padded
+// V64/V32 (M x Mp) of the mobile block and the bf16 split (Mp x Mp) of the
+// population product's weighted matrix W, zero-padded: with k and l in 128-wide
+// tiles, W_kl = V_kl when l's tile is before k's, V_kl / 2 when they are the same
+// tile, 0 after (1/2 q^T V q = sum over tiles j and tiles i <= j of the W-weighted
+// blocks; halving is exact in bf16, so hi and lo of W are those of V halved)
 __global__ void k_extract(int64_t n, int32_t M, int32_t Mp, const double* __restrict__ V,
                           const int32_t* __restrict__ mob, double* __restrict__ V64, float* __restrict__ V32,
                           __hip_bfloat16* __restrict__ Vhi, __hip_bfloat16* __restrict__ Vlo) {
@@ -107,8 +112,10 @@ __global__ void k_extract(int64_t n, int32_t M, int32_t Mp, const double* __rest
         V64[(int64_t)k * Mp + l] = v;
         V32[(int64_t)k * Mp + l] = (float)v;
     }
-    const __hip_bfloat16 hi = __float2bfloat16((float)v);
-    const double rest = v - (double)__bfloat162float(hi);
+    const int tk = k >> 7, tl = l >> 7;
+    const double w = tl < tk ? v : (tl == tk ? 0.5 * v : 0.0);
+    const __hip_bfloat16 hi = __float2bfloat16((float)w);
+    const double rest = w - (double)__bfloat162float(hi);
     Vhi[idx] = hi;
     Vlo[idx] = __float2bfloat16((float)rest);
 }
@@ -238,23 +245,89 @@ __global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fix
 
 // ------------------------------------------------------------------ chain kernels
 
-// composition check: err |= 1 when a chain's species counts per sublattice differ
-__global__ void k_check_comp(int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab,
-                             const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
-                             const uint8_t* __restrict__ occ, int32_t* __restrict__ err) {
+// Composition check of row c (Eq. 2's occupancy constraints): err |= 1 when a
+// mobile site holds a species id >= E or the species counts of a sublattice differ
+// from the problem's. One workgroup per row; each thread takes 16 consecutive
+// sites per step with 16-byte loads of the row and of the per-site class table.
+// With at most 16 (class, species) pairs the counts stay in registers, eight bits
+// per pair in two 64-bit words (moved to 32-bit counters every eight steps, before
+// a field can reach 256), then are summed over the workgroup; more pairs count
+// into an LDS histogram.
+__global__ __launch_bounds__(256) void k_check_comp(int64_t n, int32_t S, int32_t E, const int32_t* __restrict__ tab,
+                                                    const int8_t* __restrict__ site_sub,
+                                                    const uint8_t* __restrict__ occ, int32_t* __restrict__ err) {
     __shared__ int hist[kMaxSub * kMaxSpecies];
     const int64_t c = blockIdx.x;
-    for (int x = threadIdx.x; x < S * E; x += blockDim.x) hist[x] = 0;
+    const int tid = threadIdx.x;
+    const int nb = S * E;
+    for (int x = tid; x < nb; x += 256) hist[x] = 0;
     __syncthreads();
+    const uint8_t* row = occ + c * n;
+    const bool vec = (n & 15) == 0 && (((uintptr_t)row) & 15) == 0 && (((uintptr_t)site_sub) & 15) == 0;
     bool bad = false;
-    for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        const int e = occ[c * n + mob[k]];
-        if (e >= E) bad = true;
-        else atomicAdd(&hist[msub[k] * E + e], 1);
+    uint32_t tot[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) tot[b] = 0;
+    uint64_t lo = 0, hi = 0;
+    int blk = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            tot[b] += (uint32_t)((lo >> (8 * b)) & 0xffu);
+            tot[b + 8] += (uint32_t)((hi >> (8 * b)) & 0xffu);
+        }
+        lo = hi = 0;
+    };
+    for (int64_t x0 = (int64_t)tid * 16; x0 < n; x0 += 256 * 16) {
+        uint8_t e16[16];
+        int8_t s16[16];
+        if (vec) {
+            *reinterpret_cast<uint4*>(e16) = *reinterpret_cast<const uint4*>(row + x0);
+            *reinterpret_cast<uint4*>(s16) = *reinterpret_cast<const uint4*>(site_sub + x0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const bool in = x0 + k < n;
+                e16[k] = in ? row[x0 + k] : 0;
+                s16[k] = in ? site_sub[x0 + k] : (int8_t)-1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int s = s16[k], e = e16[k];
+            if (s < 0) continue;
+            if (e >= E) {
+                bad = true;
+                continue;
+            }
+            const int b = s * E + e;
+            if (nb <= 16) {
+                lo += b < 8 ? 1ull << (8 * (b & 7)) : 0ull;
+                hi += b >= 8 ? 1ull << (8 * (b & 7)) : 0ull;
+            } else {
+                atomicAdd(&hist[b], 1);
+            }
+        }
+        if (nb <= 16 && ++blk == 8) {
+            flush();
+            blk = 0;
+        }
+    }
+    if (nb <= 16) {
+        flush();
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (b < nb) {
+                uint32_t v = tot[b];
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                if ((tid & 63) == 0) atomicAdd(&hist[b], (int)v);
+            }
+        }
     }
     __syncthreads();
     const int32_t* cnt = tab + 2 + 2 * S;
-    for (int x = threadIdx.x; x < S * E; x += blockDim.x)
+    for (int x = tid; x < nb; x += 256)
         if (hist[x] != cnt[x]) bad = true;
     if (bad) atomicOr(err, 1);
 }
@@ -534,8 +607,8 @@ goac_status rows_check_launch(goac_problem* pb, int64_t P, const uint8_t* occ, i
     const ProblemDev& d = pb->d;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, flag, 1);
     if (P > 0)
-        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)P), dim3(256), 0, ctx->stream, d.n, d.M, d.S, d.E, d.tab,
-                           d.mob, d.msub, occ, flag);
+        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)P), dim3(256), 0, ctx->stream, d.n, d.S, d.E, d.tab,
+                           d.site_sub, occ, flag);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
@@ -549,7 +622,18 @@ goac_status rows_check_enqueue(goac_problem* pb, int64_t P, const uint8_t* occ) 
 }
 
 goac_status rows_check_wait(goac_ctx* ctx, const char* who) {
-    GOAC_HIP(ctx, hipEventSynchronize(ctx->chk_ev));
+    // the check is short: poll its event for up to 2 ms, so the host answers at
+    // once and the next call's kernels follow without a gap, then block
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t q = hipEventQuery(ctx->chk_ev);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) GOAC_HIP(ctx, q);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+            GOAC_HIP(ctx, hipEventSynchronize(ctx->chk_ev));
+            break;
+        }
+    }
     if (*ctx->chk_host)
         return fail(ctx, GOAC_EINVAL,
                     std::string(who) + ": an occupation holds an unknown species or breaks the problem's composition");
@@ -766,7 +850,8 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     // derived device-only arrays
     const int32_t nf = (int32_t)fixed.size();
     ArenaPlan ap;
-    const size_t o_mob = ap.take(M * 4), o_msub = ap.take(Mp), o_ref = ap.take(n), o_chg = ap.take(E * 8),
+    const size_t o_mob = ap.take(M * 4), o_msub = ap.take(Mp), o_ref = ap.take(n), o_ssub = ap.take(n),
+                 o_chg = ap.take(E * 8),
                  o_dq = ap.take(S * E * 8), o_tab = ap.take(tab.size() * 4), o_spos = ap.take(M * 4),
                  o_sinv = ap.take(M * 4), o_site = ap.take(M * 4), o_fix = ap.take((nf + 1) * 4),
                  o_fq = ap.take((nf + 1) * 8),
@@ -786,6 +871,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     d.mob = (int32_t*)(base + o_mob);
     d.msub = (uint8_t*)(base + o_msub);
     d.ref_occ = (uint8_t*)(base + o_ref);
+    d.site_sub = (int8_t*)(base + o_ssub);
     d.charge = (double*)(base + o_chg);
     d.dq = (double*)(base + o_dq);
     d.tab = (int32_t*)(base + o_tab);
@@ -814,6 +900,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     std::memcpy(img.data() + o_mob, mob.data(), M * 4);
     std::memcpy(img.data() + o_msub, msub.data(), Mp);
     std::memcpy(img.data() + o_ref, species, n);
+    for (int64_t x = 0; x < n; ++x) reinterpret_cast<int8_t*>(img.data() + o_ssub)[x] = (int8_t)(sub[x] < 0 ? -1 : sub[x]);
     std::memcpy(img.data() + o_chg, charge, E * 8);
     std::memcpy(img.data() + o_dq, dq.data(), S * E * 8);
     std::memcpy(img.data() + o_tab, tab.data(), tab.size() * 4);
@@ -1228,8 +1315,8 @@ static goac_status chains_fill(goac_chains* ch, const uint8_t* occ, bool reload)
         const ProblemDev& d = ch->pbs[i]->d;
         const int64_t Ci = ch->count[i];
         if (Ci == 0) continue;
-        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)Ci), dim3(256), 0, sm, d.n, d.M, d.S, d.E, d.tab, d.mob,
-                           d.msub, occ + ch->occ_row_off[i], err);
+        hipLaunchKernelGGL(k_check_comp, dim3((unsigned)Ci), dim3(256), 0, sm, d.n, d.S, d.E, d.tab, d.site_sub,
+                           occ + ch->occ_row_off[i], err);
     }
     GOAC_CHECK_LAUNCH(ctx);
     int32_t herr = 0;

@@ -112,10 +112,12 @@ struct ProblemDev {
     int32_t* mob;        // M: site index of mobile position k (ascending)
     uint8_t* msub;       // Mp: sublattice of position k (0 beyond M)
     uint8_t* ref_occ;    // n: the problem's occupation (fixed-site species)
+    int8_t* site_sub;    // n: site class of each site (-1 fixed)
     double* V64;         // M x Mp: mobile block, FP64 (zero beyond M)
     float* V32;          // M x Mp: FP32 rounding of V64
-    __hip_bfloat16* Vhi; // Mp x Mp: bf16(V)
-    __hip_bfloat16* Vlo; // Mp x Mp: bf16(V - Vhi)
+    __hip_bfloat16* Vhi; // Mp x Mp: bf16(W), W = V block-lower-triangular with halved
+                         // diagonal 128 x 128 blocks (the population product's weights)
+    __hip_bfloat16* Vlo; // Mp x Mp: bf16(W - Vhi)
     double* diag;        // M
     float* rowmax;       // M: max_k |V_ik|, rounded up
     double* rowabs;      // M: sum_k |V_ik|

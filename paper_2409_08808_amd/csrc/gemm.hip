@@ -165,34 +165,33 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 }
 
 // ------------------------------------------------------------------ bf16 hi+lo population GEMM
-// E_p - lin_p - E~ = 1/2 dQ_p^T V dQ_p with V = Vhi + Vlo symmetric (so its rows
-// serve as columns), bf16 inputs, FP32 accumulation on v_mfma_f32_32x32x16_bf16.
-// The (k, n) plane is cut into blocks of KB = KT n-tiles each way; with
-// T_ij = sum_{k in block i, n in block j} dQ[p][k] V[k][n] dQ[p][n] and T_ij = T_ji,
-//   1/2 dQ^T V dQ = sum_i 1/2 T_ii + sum_{i<j} T_ij,
-// so only the blocks with i <= j are formed (about half the matrix work and the
-// V traffic). A workgroup takes one p-tile, one n-tile of block j and the K range
-// of block i, and its fused epilogue writes
-//   part[t][p] = w sum_{n in tile} dQ[p][n] Phi_slice[p][n],  w = 1/2 (i = j), 1 (i < j)
-// in FP32 within the tile (dQ is a small integer; the error stays orders of
-// magnitude below the FP32 accumulation of Phi itself) and FP64 across tiles. The
-// linear term dQ . ht is added in FP64 by k_pop_finalize.
+// E_p - lin_p - E~ = 1/2 dQ_p^T V dQ_p. With the mobile positions in 128-wide
+// tiles, 1/2 dQ^T V dQ = sum over n-tiles j and k-tiles i <= j of
+//   sum_{n in j} dQ_pn sum_{k in i} W_nk dQ_pk,
+// W = V for i < j and V / 2 for i = j (stored so, hi and lo in bf16: k_extract),
+// so every (p-tile, n-tile j, k-tile i <= j) unit has weight one and the symmetric
+// half of the matrix work is all there is. The units are enumerated p-tile, then
+// j, then i (i fastest), and a grid of G workgroups takes equal contiguous shares
+// of them (stream-K: no partial last wave however the units fall). A share splits
+// into runs, one per (p-tile, j) it touches; a run accumulates its k-tiles on the
+// matrix cores (bf16 inputs, v_mfma_f32_32x32x16_bf16, FP32 accumulation) and its
+// fused epilogue writes the run's row sums sum_{n in j} dQ_pn Phi_pn (FP32 within
+// the tile, dQ a small integer) to part, the run's p-tile to run_mt. k_pop_finalize
+// adds a row's runs in a fixed order, so a given grid gives the same sums always.
 // Tile 256 (p) x 128 (n) x 32 (k), 256 threads = 2 x 2 waves, each wave 128 x 64 =
-// 4 x 2 accumulators, each fed by the hi and the lo operand: 16 MFMAs per 8 LDS
-// operand reads (the hi/lo pair doubles the n-side operand, so the wave tile is
-// long in p). The next K stage is fetched into registers while the matrix cores
-// work on the current one; double-buffered LDS (80 KiB, two workgroups per
-// compute unit), one barrier per stage. Workgroup id -> (p-tile fastest, then the
-// (n-tile, K block) pairs in n-tile order, n-tile t having t / KT + 1 of them).
+// 4 x 2 accumulators fed by the hi and the lo operand: 16 MFMAs per 8 LDS operand
+// reads. The next K stage is fetched into registers while the matrix cores work
+// on the current one; double-buffered LDS (80 KiB, two workgroups per compute
+// unit), one barrier per stage.
 constexpr int PB_BM = 256, PB_BN = 128, PB_BK = 32, PB_LD = PB_BK + 8, PB_DLD = PB_BN + 8;
 constexpr int kPopLds = 2 * (PB_BM + 2 * PB_BN) * PB_LD * 2;   // 80 KiB
 static_assert(PB_BM * PB_DLD * 2 + PB_BM * 2 * 8 <= kPopLds, "epilogue staging exceeds the stage buffers");
 
-__global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32_t Mp,
-                                                     const __hip_bfloat16* __restrict__ dQ,
+__global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, const __hip_bfloat16* __restrict__ dQ,
                                                      const __hip_bfloat16* __restrict__ Vhi,
                                                      const __hip_bfloat16* __restrict__ Vlo,
-                                                     double* __restrict__ part, int32_t MT, int32_t KT) {
+                                                     double* __restrict__ part, int32_t* __restrict__ run_mt,
+                                                     int32_t NT, int64_t U, int32_t G, int32_t R) {
     // operand stages during the K loop; the epilogue reuses the same bytes for the
     // tile's dQ block and the row sums
     __shared__ __align__(16) unsigned char smem[kPopLds];
@@ -201,165 +200,177 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t M, int32
     auto Ls = reinterpret_cast<__hip_bfloat16 (*)[PB_BN][PB_LD]>(smem + 2 * (PB_BM + PB_BN) * PB_LD * 2);
     auto Ds = reinterpret_cast<__hip_bfloat16 (*)[PB_DLD]>(smem);
     auto red = reinterpret_cast<double (*)[2]>(smem + PB_BM * PB_DLD * 2);
-    const int u = (int)blockIdx.x;
-    const int mt = u % MT;
-    const int slot = u / MT;   // the (n-tile, K block) pair, also part's row
-    int pr = slot, nt = 0;
-    while (pr >= nt / KT + 1) {
-        pr -= nt / KT + 1;
-        ++nt;
-    }
-    const int kb_len = KT * PB_BN;
-    const int kbeg = pr * kb_len;
-    const double wgt = pr < nt / KT ? 1.0 : 0.5;
-    const int64_t m0 = (int64_t)mt * PB_BM;
-    const int n0 = nt * PB_BN;
-    const int kend = kbeg + kb_len < Mp ? kbeg + kb_len : Mp;
+    const int g = (int)blockIdx.x;
+    const int64_t u_end = U * (g + 1) / G;
+    const int64_t Umt = (int64_t)NT * (NT + 1) / 2;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    f32x16 acc[4][2];
+    int r = 0;
+    for (int64_t u = U * g / G; u < u_end; ++r) {
+        // the run from unit u: p-tile mt, n-tile j, k-tiles i0 .. i0 + len - 1 of j
+        const int mt = (int)(u / Umt);
+        const int64_t rem = u - (int64_t)mt * Umt;
+        int j = (int)((sqrt(8.0 * (double)rem + 1.0) - 1.0) * 0.5);
+        while ((int64_t)j * (j + 1) / 2 > rem) --j;
+        while ((int64_t)(j + 1) * (j + 2) / 2 <= rem) ++j;
+        const int i0 = (int)(rem - (int64_t)j * (j + 1) / 2);
+        const int len = (int)std::min<int64_t>(u_end - u, (int64_t)(j + 1 - i0));
+        u += len;
+        const int kbeg = i0 * PB_BN;
+        const int kend = (i0 + len) * PB_BN < Mp ? (i0 + len) * PB_BN : Mp;
+        const int64_t m0 = (int64_t)mt * PB_BM;
+        const int n0 = j * PB_BN;
+        f32x16 acc[4][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
-    // loader: the p-tile is 256 rows x 32 k = 1024 chunks of 8 bf16 (four per
-    // thread), each n-tile 128 rows x 32 k (two per thread)
-    uint4 ra[4], rh[2], rl[2];
-    auto fetch = [&](int k0) {
+            for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
+        // loader: the p-tile is 256 rows x 32 k = 1024 chunks of 8 bf16 (four per
+        // thread), each n-tile 128 rows x 32 k (two per thread)
+        uint4 ra[4], rh[2], rl[2];
+        auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int idx = tid + q * 256;
-            const int r = idx >> 2;
-            const int c = (idx & 3) * 8;
-            const int64_t gp = m0 + r;
-            ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int idx = tid + q * 256;
+                const int rr = idx >> 2;
+                const int c = (idx & 3) * 8;
+                const int64_t gp = m0 + rr;
+                ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
+            }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + q * 256;
-            const int r = idx >> 2;
-            const int c = (idx & 3) * 8;
-            const int gn = n0 + r;
-            rh[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vhi + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
-            rl[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vlo + (int64_t)gn * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
-        }
-    };
-    auto stash = [&](int buf) {
+            for (int q = 0; q < 2; ++q) {
+                const int idx = tid + q * 256;
+                const int rr = idx >> 2;
+                const int c = (idx & 3) * 8;
+                const int gn = n0 + rr;
+                rh[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vhi + (int64_t)gn * Mp + k0 + c)
+                                : make_uint4(0, 0, 0, 0);
+                rl[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vlo + (int64_t)gn * Mp + k0 + c)
+                                : make_uint4(0, 0, 0, 0);
+            }
+        };
+        auto stash = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int idx = tid + q * 256;
-            *reinterpret_cast<uint4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int idx = tid + q * 256;
+                *reinterpret_cast<uint4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
+            }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + q * 256;
-            *reinterpret_cast<uint4*>(&Hs[buf][idx >> 2][(idx & 3) * 8]) = rh[q];
-            *reinterpret_cast<uint4*>(&Ls[buf][idx >> 2][(idx & 3) * 8]) = rl[q];
-        }
-    };
-    if (kbeg < kend) {
+            for (int q = 0; q < 2; ++q) {
+                const int idx = tid + q * 256;
+                *reinterpret_cast<uint4*>(&Hs[buf][idx >> 2][(idx & 3) * 8]) = rh[q];
+                *reinterpret_cast<uint4*>(&Ls[buf][idx >> 2][(idx & 3) * 8]) = rl[q];
+            }
+        };
         fetch(kbeg);
         stash(0);
-    }
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += PB_BK) {
-        const bool more = k0 + PB_BK < kend;
-        if (more) fetch(k0 + PB_BK);
-#pragma unroll
-        for (int ks = 0; ks < PB_BK; ks += 16) {
-            const int kk = ks + 8 * (lane >> 5);
-            bf16x8 av[4], hv[2], lv[2];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 128 + a * 32 + (lane & 31)][kk]);
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                hv[b] = *reinterpret_cast<const bf16x8*>(&Hs[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
-                lv[b] = *reinterpret_cast<const bf16x8*>(&Ls[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], hv[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], lv[b], acc[a][b], 0, 0, 0);
-        }
-        if (more) stash(buf ^ 1);
         __syncthreads();
-        buf ^= 1;
-    }
-    // epilogue. The tile's dQ block (256 p x 128 n) is staged in LDS with 16-byte
-    // loads. Lane holds D[i][j] of each 32 x 32 block, j = lane % 32,
-    // i = 8 (v / 4) + 4 (lane / 32) + v % 4; per 32-row block the lane forms
-    // x_v = sum_b dQ[i][j_b] D_b[i][j] and a halving butterfly over the 32 lanes of
-    // its half (masks 16, 8, 4, 2, 1, each step keeping half of the rows) leaves
-    // row v(lane) summed over all 32 columns in lanes 2c and 2c + 1 (fixed order,
-    // deterministic).
-    for (int x = tid; x < PB_BM * (PB_BN / 8); x += 256) {
-        const int r = x / (PB_BN / 8), c = (x % (PB_BN / 8)) * 8;
-        const int64_t gp = m0 + r;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gp < P && n0 + c < Mp) v = *reinterpret_cast<const uint4*>(dQ + gp * Mp + n0 + c);
-        *reinterpret_cast<uint4*>(&Ds[r][c]) = v;
-    }
-    __syncthreads();
-    const int c32 = lane & 31, h = lane >> 5;
-    const int vkeep = ((c32 >> 4) & 1) * 8 + ((c32 >> 3) & 1) * 4 + ((c32 >> 2) & 1) * 2 + ((c32 >> 1) & 1);
+        int buf = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += PB_BK) {
+            const bool more = k0 + PB_BK < kend;
+            if (more) fetch(k0 + PB_BK);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        float x[16];
+            for (int ks = 0; ks < PB_BK; ks += 16) {
+                const int kk = ks + 8 * (lane >> 5);
+                bf16x8 av[4], hv[2], lv[2];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = 8 * (v >> 2) + 4 * h + (v & 3);
-            const int r = wm * 128 + a * 32 + i;
-            float s2 = 0.0f;
+                for (int a = 0; a < 4; ++a)
+                    av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 128 + a * 32 + (lane & 31)][kk]);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) s2 += __bfloat162float(Ds[r][wn * 64 + b * 32 + c32]) * acc[a][b][v];
-            x[v] = s2;
+                for (int b = 0; b < 2; ++b) {
+                    hv[b] = *reinterpret_cast<const bf16x8*>(&Hs[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
+                    lv[b] = *reinterpret_cast<const bf16x8*>(&Ls[buf][wn * 64 + b * 32 + (lane & 31)][kk]);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], hv[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], lv[b], acc[a][b], 0, 0, 0);
+            }
+            if (more) stash(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
         }
+        // epilogue. The tile's dQ block (256 p x 128 n) is staged in LDS with 16-byte
+        // loads. Lane holds D[i][j] of each 32 x 32 block, j = lane % 32,
+        // i = 8 (v / 4) + 4 (lane / 32) + v % 4; per 32-row block the lane forms
+        // x_v = sum_b dQ[i][j_b] D_b[i][j] and a halving butterfly over the 32 lanes of
+        // its half (masks 16, 8, 4, 2, 1, each step keeping half of the rows) leaves
+        // row v(lane) summed over all 32 columns in lanes 2c and 2c + 1 (fixed order,
+        // deterministic).
+        for (int x = tid; x < PB_BM * (PB_BN / 8); x += 256) {
+            const int rr = x / (PB_BN / 8), c = (x % (PB_BN / 8)) * 8;
+            const int64_t gp = m0 + rr;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gp < P && n0 + c < Mp) v = *reinterpret_cast<const uint4*>(dQ + gp * Mp + n0 + c);
+            *reinterpret_cast<uint4*>(&Ds[rr][c]) = v;
+        }
+        __syncthreads();
+        const int c32 = lane & 31, h = lane >> 5;
+        const int vkeep = ((c32 >> 4) & 1) * 8 + ((c32 >> 3) & 1) * 4 + ((c32 >> 2) & 1) * 2 + ((c32 >> 1) & 1);
 #pragma unroll
-        for (int w = 8; w >= 1; w >>= 1) {
-            const bool low = (c32 & (2 * w)) == 0;   // keep rows v < w of the current block
+        for (int a = 0; a < 4; ++a) {
+            float x[16];
 #pragma unroll
-            for (int v = 0; v < w; ++v) {
-                const float send = low ? x[v + w] : x[v];
-                const float recv = __shfl_xor(send, 2 * w, 64);
-                x[v] = (low ? x[v] : x[v + w]) + recv;
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * h + (v & 3);
+                const int rr = wm * 128 + a * 32 + i;
+                float s2 = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) s2 += __bfloat162float(Ds[rr][wn * 64 + b * 32 + c32]) * acc[a][b][v];
+                x[v] = s2;
+            }
+#pragma unroll
+            for (int w = 8; w >= 1; w >>= 1) {
+                const bool low = (c32 & (2 * w)) == 0;   // keep rows v < w of the current block
+#pragma unroll
+                for (int v = 0; v < w; ++v) {
+                    const float send = low ? x[v + w] : x[v];
+                    const float recv = __shfl_xor(send, 2 * w, 64);
+                    x[v] = (low ? x[v] : x[v + w]) + recv;
+                }
+            }
+            const float tot = x[0] + __shfl_xor(x[0], 1, 64);
+            if ((c32 & 1) == 0) {
+                const int i = 8 * (vkeep >> 2) + 4 * h + (vkeep & 3);
+                red[wm * 128 + a * 32 + i][wn] = (double)tot;
             }
         }
-        const float tot = x[0] + __shfl_xor(x[0], 1, 64);
-        if ((c32 & 1) == 0) {
-            const int i = 8 * (vkeep >> 2) + 4 * h + (vkeep & 3);
-            red[wm * 128 + a * 32 + i][wn] = (double)tot;
-        }
+        __syncthreads();
+        const int64_t slot = (int64_t)g * R + r;
+        part[slot * PB_BM + tid] = red[tid][0] + red[tid][1];
+        if (tid == 0) run_mt[slot] = mt;
+        __syncthreads();   // the LDS is the next run's stage buffer
     }
-    __syncthreads();
-    const int64_t gp = m0 + tid;
-    if (gp < P) part[(int64_t)slot * P + gp] = wgt * (red[tid][0] + red[tid][1]);
+    for (; r < R; ++r)
+        if (tid == 0) run_mt[(int64_t)g * R + r] = -1;
 }
 
-// E[p] = E~ + lin[p] + sum over (column tile, K slice) t of part[t][p], with
-// lin[p] = sum_k dQ[p][k] ht[k] (FP64) from the row builder or, when it did not
-// form it, here: one wavefront per row, each lane sums its strided share in
-// order, then a fixed butterfly
-__global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int32_t Mp, int32_t n_tiles,
+// E[p] = E~ + lin[p] + the row sums of the runs on p's p-tile, with lin[p] =
+// sum_k dQ[p][k] ht[k] (FP64) from the row builder or, when it did not form it,
+// here: one wavefront per row, each lane sums its strided share in order, then a
+// fixed butterfly
+__global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int32_t Mp, int32_t runs,
                                                       const __hip_bfloat16* __restrict__ dQ,
                                                       const double* __restrict__ ht, const double* __restrict__ part,
+                                                      const int32_t* __restrict__ run_mt,
                                                       const double* __restrict__ lin, const double* __restrict__ Ed,
                                                       double* __restrict__ E, const int32_t* __restrict__ gate) {
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (p >= P || (gate && *gate)) return;
+    const int mt = (int)(p / PB_BM), loc = (int)(p - (int64_t)mt * PB_BM);
     double s = 0.0;
     if (!lin)
         for (int k = lane; k < M; k += 64) s += (double)__bfloat162float(dQ[p * Mp + k]) * ht[k];
-    for (int t = lane; t < n_tiles; t += 64) s += part[(int64_t)t * P + p];
+    for (int t = lane; t < runs; t += 64)
+        if (run_mt[t] == mt) s += part[(int64_t)t * PB_BM + loc];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) E[p] = Ed[1] + (lin ? lin[p] + s : s);
@@ -517,56 +528,59 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
     return GOAC_OK;
 }
 
-// n-tiles per K block of the mixed product for P rows and the number of (n-tile,
-// K block) pairs it forms: the requested KT, else the one set or tuned for this
-// population size, else the one that minimises the estimated makespan
-static int32_t pop_kt_choice(const goac_problem* pb, int64_t P, int32_t kt_req, int64_t* n_pairs) {
-    const ProblemDev& d = pb->d;
-    const int32_t NT = (d.Mp + PB_BN - 1) / PB_BN;
-    const int64_t MT = (P + PB_BM - 1) / PB_BM;
-    // the symmetric form: K blocks of KT n-tiles; pairs(KT) = sum_t (t / KT + 1).
-    // KT is the requested one, else the one set or tuned for this population size,
-    // else the one that minimises the estimated makespan: rounds of two workgroups
-    // per compute unit times the K length of one plus a fixed cost of 128 K steps
-    // (measured on the 4x4x4, 8x8x8 and 16x16x8 rock-salt populations); ties go to
-    // the longer K
-    auto pairs = [&](int kt) {
-        int64_t n = 0;
-        for (int t = 0; t < NT; ++t) n += t / kt + 1;
-        return n;
-    };
-    int KT = 1;
+// Grid of the mixed product for P rows: U units (p-tile, n-tile j, k-tile i <= j)
+// shared by G workgroups, and R, the most runs one share splits into. G is the
+// number of units up to two workgroups per compute unit (more workgroups measured
+// faster at every population size tried), divided by the tile setting kt when one
+// is set or tuned.
+struct PopPlan {
+    int32_t NT = 0, MT = 0, G = 0, R = 0;
+    int64_t U = 0;
+};
+
+static int32_t pop_max_runs(int64_t U, int64_t Umt, int64_t G) {
+    int32_t R = 1;
+    for (int64_t g = 0; g < G; ++g) {
+        const int64_t u0 = U * g / G, u1 = U * (g + 1) / G;
+        int32_t r = 0;
+        for (int64_t u = u0; u < u1; ++r) {
+            const int64_t mt = u / Umt, rem = u - mt * Umt;
+            int64_t j = (int64_t)((std::sqrt(8.0 * (double)rem + 1.0) - 1.0) * 0.5);
+            while (j * (j + 1) / 2 > rem) --j;
+            while ((j + 1) * (j + 2) / 2 <= rem) ++j;
+            u += std::min<int64_t>(u1 - u, j + 1 - (rem - j * (j + 1) / 2));
+        }
+        R = std::max(R, r);
+    }
+    return R;
+}
+
+static PopPlan pop_plan(const goac_problem* pb, int64_t P, int32_t kt_req) {
+    PopPlan pl;
+    pl.NT = (pb->d.Mp + PB_BN - 1) / PB_BN;
+    pl.MT = (int32_t)((P + PB_BM - 1) / PB_BM);
+    const int64_t Umt = (int64_t)pl.NT * (pl.NT + 1) / 2;
+    pl.U = Umt * pl.MT;
     if (kt_req <= 0) {
         const auto it = pb->pop_kt.find(P);
-        if (it != pb->pop_kt.end()) kt_req = it->second;
+        kt_req = it != pb->pop_kt.end() ? it->second : 1;
     }
-    if (kt_req > 0) {
-        KT = kt_req;
-    } else {
-        int64_t best_cost = -1;
-        for (int kt = 1; kt <= 8 && (kt == 1 || kt <= NT); kt *= 2) {
-            const int64_t wg = MT * pairs(kt);
-            const int64_t rounds = (wg + 2 * pb->ctx->num_cus - 1) / (2 * pb->ctx->num_cus);
-            const int64_t cost = rounds * ((int64_t)kt * PB_BN + 128);
-            if (best_cost < 0 || cost <= best_cost) {
-                best_cost = cost;
-                KT = kt;
-            }
-        }
-    }
-    *n_pairs = pairs(KT);
-    return KT;
+    const int64_t slots = 2 * (int64_t)std::max(1, pb->ctx->num_cus);
+    pl.G = (int32_t)std::min<int64_t>(pl.U, std::max<int64_t>(1, slots / kt_req));
+    pl.R = pop_max_runs(pl.U, Umt, pl.G);
+    return pl;
 }
 
 size_t energies_scratch_bytes(const goac_problem* pb, int64_t P, goac_precision prec) {
     const ProblemDev& d = pb->d;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     if (prec == GOAC_MIXED) {
-        int64_t n_parts = 0;
-        (void)pop_kt_choice(pb, P, 0, &n_parts);
+        const PopPlan pl = pop_plan(pb, P, 0);
+        const size_t runs = (size_t)pl.G * pl.R;
         const size_t dq_bytes = al((size_t)P * d.Mp * sizeof(__hip_bfloat16));
-        const size_t part_bytes = al((size_t)P * n_parts * sizeof(double));
-        return al(dq_bytes + part_bytes + (size_t)P * sizeof(double));
+        const size_t part_bytes = al(runs * PB_BM * sizeof(double));
+        const size_t mt_bytes = al(runs * sizeof(int32_t));
+        return al(dq_bytes + part_bytes + mt_bytes + (size_t)P * sizeof(double));
     }
     const size_t qb = al((size_t)P * d.Mp * sizeof(double));
     const int splits = dgemm_splits(pb->ctx, P, d.M, d.Mp, nullptr, false);
@@ -577,22 +591,22 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
                            const int32_t* gate, WsSource* src) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
-    const int64_t MT = (P + PB_BM - 1) / PB_BM;
-    int64_t n_pairs = 0;
-    const int32_t KT = pop_kt_choice(pb, P, kt_req, &n_pairs);
-    const int64_t total = MT * n_pairs;
-    if (total > ((int64_t)1 << 30)) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
-    const int32_t n_parts = (int32_t)n_pairs;
+    const PopPlan pl = pop_plan(pb, P, kt_req);
+    const int64_t runs = (int64_t)pl.G * pl.R;
+    if (pl.U > ((int64_t)1 << 40) || runs > ((int64_t)1 << 30))
+        return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
     const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
-    const size_t part_bytes = round_up((size_t)P * n_parts * sizeof(double), 256);
+    const size_t part_bytes = round_up((size_t)runs * PB_BM * sizeof(double), 256);
+    const size_t mt_bytes = round_up((size_t)runs * sizeof(int32_t), 256);
     WsSource own{ctx};
     void* ws = nullptr;
-    GOAC_TRY((src ? src : &own)->get(0, dq_bytes + part_bytes + (size_t)P * sizeof(double), &ws));
+    GOAC_TRY((src ? src : &own)->get(0, dq_bytes + part_bytes + mt_bytes + (size_t)P * sizeof(double), &ws));
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
     double* part = (double*)((char*)ws + dq_bytes);
+    int32_t* run_mt = (int32_t*)((char*)ws + dq_bytes + part_bytes);
     double* lin = nullptr;
     if (d.n <= kDqStageMax) {
-        lin = (double*)((char*)ws + dq_bytes + part_bytes);
+        lin = (double*)((char*)ws + dq_bytes + part_bytes + mt_bytes);
         // rows per workgroup: the position tables are read once for all of them
         const int64_t ld = round_up(d.n, 16);
         const int R = (P >= 4 * 2 * (int64_t)ctx->num_cus && 4 * ld <= 64 * 1024) ? 4
@@ -611,11 +625,11 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
         hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream,
                            P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ, gate);
     GOAC_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)total), dim3(256), 0, ctx->stream, P, d.M, d.Mp, dQ, d.Vhi, d.Vlo,
-                       part, (int32_t)MT, KT);
+    hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)pl.G), dim3(256), 0, ctx->stream, P, d.Mp, dQ, d.Vhi, d.Vlo, part,
+                       run_mt, pl.NT, pl.U, pl.G, pl.R);
     GOAC_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
-                       n_parts, dQ, d.ht, part, lin, d.Ed, E, gate);
+                       (int32_t)runs, dQ, d.ht, part, run_mt, lin, d.Ed, E, gate);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }
