@@ -155,9 +155,14 @@ goac_status goac_init_occupations(goac_problem* pb, int64_t C, uint64_t seed, ui
  * reduced form of Eq. 2, E_p = E_ff + q^T h + 1/2 q^T V_mm q over the mobile
  * block (fixed-site entries of occ are ignored).
  *   GOAC_FP64  : FP64 matrix-core product Q V_mm and FP64 row dot.
- *   GOAC_MIXED : q = c + dq with the exact integer shift c; Phi = dQ V_hi + dQ
- *                V_lo on bfloat16 matrix cores with FP32 accumulation, then
- *                E_p = E~ + sum_k dq_k (h~_k + Phi_k / 2) in FP64.
+ *   GOAC_MIXED : q = c + dq with the exact integer shift c; the quadratic part
+ *                1/2 dq^T V_mm dq as dQ W dQ over the lower block triangle W of
+ *                V_mm (diagonal 128-blocks halved), split W = W_hi + W_lo in
+ *                bfloat16, on matrix cores with FP32 accumulation per 128 x 128
+ *                block; E_p = E~ + sum_k dq_k h~_k + that part, the row sums
+ *                added as 64-bit fixed point (a power-of-two scale per problem),
+ *                so a call repeats bit-exactly whatever order the device runs
+ *                the blocks in.
  *   occ_dev : P x n uint8 (P <= 2^30);  E_dev : P FP64 output.
  * The rows are checked first (conventions above). The energy kernels are queued
  * right behind the check and skip all work when it fails, so the call waits for
@@ -174,9 +179,9 @@ goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
  * every GPU the library runs on holds until the process ends. No device or pinned
  * memory is allocated. The call waits for the stream (it reads the row check back
  * into host memory of its own stack).
- *   Limit: the energies of P rows must fit the array (about P x M x 2 bytes plus
- *   partial sums for GOAC_MIXED, P x M x 16 bytes plus split-K partials for
- *   GOAC_FP64); larger calls return EINVAL and compute nothing.
+ *   Limit: the energies of P rows must fit the array (about P x (M x 2 + 8) bytes
+ *   for GOAC_MIXED, P x M x 16 bytes plus split-K partials for GOAC_FP64);
+ *   larger calls return EINVAL and compute nothing.
  *   Concurrency: all calls on one GPU share its array, which keeps the last call's
  *   contents; calls that overlap on one GPU (other host threads, other streams)
  *   race and are not allowed.
@@ -184,10 +189,11 @@ goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
 goac_status goac_energies_noalloc(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
                                   goac_precision prec, double* E_dev);
 
-/* Tile of the GOAC_MIXED population product for populations of P rows: kt n-tiles
- * of 128 positions per K block (1, 2, 4 or 8, at most the problem's number of
- * n-tiles unless 1; 0 returns P to the built-in cost model). The energies differ
- * between tiles only by the FP32 accumulation order, within the mixed bound.
+/* Grid of the GOAC_MIXED population product for populations of P rows: the
+ * product's (p-tile, n-tile, k-tile) units are shared by 2 x (compute units) / kt
+ * workgroups, kt = 1, 2, 4 or 8 (at most the problem's number of 128-position
+ * n-tiles unless 1; 0 returns P to the default, kt = 1). The energies differ
+ * between settings only by the FP32 accumulation order, within the mixed bound.
  * Host-side; errors: EINVAL. */
 goac_status goac_energies_tile(goac_problem* pb, int64_t P, int32_t kt);
 

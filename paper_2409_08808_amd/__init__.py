@@ -241,7 +241,7 @@ class Problem:
         return out
 
     def energies_tile(self, P, kt):
-        """Set the mixed population product's tile for P rows (0: the cost model)."""
+        """Set the mixed population product's grid setting for P rows (0: the default)."""
         self.ctx.check(load().goac_energies_tile(self._h, P, kt))
 
     def energies_autotune(self, occ):

@@ -95,20 +95,20 @@ goac_status workspace(goac_ctx* ctx, int slot, size_t bytes, void** out) {
 
 // ------------------------------------------------------------------ problem derivation kernels
 
-// V64/V32 (M x Mp) of the mobile block and the bf16 split (Mp x Mp) of the
+// V64/V32 (M x Mp) of the mobile block and the bf16 split (Mq x Mq) of the
 // population product's weighted matrix W, zero-padded: with k and l in 128-wide
 // tiles, W_kl = V_kl when l's tile is before k's, V_kl / 2 when they are the same
 // tile, 0 after (1/2 q^T V q = sum over tiles j and tiles i <= j of the W-weighted
 // blocks; halving is exact in bf16, so hi and lo of W are those of V halved)
-__global__ void k_extract(int64_t n, int32_t M, int32_t Mp, const double* __restrict__ V,
+__global__ void k_extract(int64_t n, int32_t M, int32_t Mp, int32_t Mq, const double* __restrict__ V,
                           const int32_t* __restrict__ mob, double* __restrict__ V64, float* __restrict__ V32,
                           __hip_bfloat16* __restrict__ Vhi, __hip_bfloat16* __restrict__ Vlo) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)Mp * Mp) return;
-    const int k = (int)(idx / Mp), l = (int)(idx - (int64_t)k * Mp);
+    if (idx >= (int64_t)Mq * Mq) return;
+    const int k = (int)(idx / Mq), l = (int)(idx - (int64_t)k * Mq);
     double v = 0.0;
     if (k < M && l < M) v = V[(int64_t)mob[k] * n + mob[l]];
-    if (k < M) {
+    if (k < M && l < Mp) {
         V64[(int64_t)k * Mp + l] = v;
         V32[(int64_t)k * Mp + l] = (float)v;
     }
@@ -198,19 +198,25 @@ __global__ __launch_bounds__(256) void k_fixed_energy(int64_t n, const int32_t* 
 
 // one workgroup, fixed-order sums (per-thread strided partials, then a tree):
 //   out[0] = E_ff = 1/2 sum efix,  out[1] = E~ = E_ff + sum c_k h_k + 1/2 sum c_k vc_k,
-//   phibar[s] = mean of phiref over sublattice s; ht_k = h_k + vc_k
+//   phibar[s] = mean of phiref over sublattice s; ht_k = h_k + vc_k;
+//   out[2] = 2^sc, out[3] = 2^-sc: the scale of the population product's 64-bit
+//   fixed-point row sums, sc the largest integer with 2^sc B < 2^61 for the bound
+//   B = dqmax^2 sum_k rowabs_k + dqmax sum_k |ht_k| + 1 on the absolute terms of a
+//   row's linear and quadratic parts (dqmax = the largest |charge - shift|)
 __global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fixed, int32_t S,
                                                         const double* __restrict__ efix,
                                                         const double* __restrict__ cvec,
                                                         const double* __restrict__ h,
                                                         const double* __restrict__ vc,
                                                         const double* __restrict__ phiref,
-                                                        const uint8_t* __restrict__ msub, double* __restrict__ ht,
-                                                        double* __restrict__ phibar, double* __restrict__ out) {
-    __shared__ double red[3 + kMaxSub][256];
+                                                        const uint8_t* __restrict__ msub,
+                                                        const double* __restrict__ rowabs, double dqmax,
+                                                        double* __restrict__ ht, double* __restrict__ phibar,
+                                                        double* __restrict__ out) {
+    __shared__ double red[5 + kMaxSub][256];
     __shared__ int cnt[kMaxSub][256];
     const int t = threadIdx.x;
-    double e = 0.0, ch = 0.0, cvc = 0.0;
+    double e = 0.0, ch = 0.0, cvc = 0.0, rab = 0.0, hab = 0.0;
     double acc[kMaxSub];
     int nc[kMaxSub];
     for (int s = 0; s < kMaxSub; ++s) { acc[s] = 0.0; nc[s] = 0; }
@@ -219,6 +225,8 @@ __global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fix
         ch += cvec[k] * h[k];
         cvc += cvec[k] * vc[k];
         ht[k] = h[k] + vc[k];
+        rab += rowabs[k];
+        hab += fabs(ht[k]);
         const int s = msub[k];
         for (int q = 0; q < kMaxSub; ++q)
             if (q == s) { acc[q] += phiref[k]; nc[q] += 1; }
@@ -227,10 +235,12 @@ __global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fix
     red[1][t] = ch;
     red[2][t] = cvc;
     for (int s = 0; s < kMaxSub; ++s) { red[3 + s][t] = acc[s]; cnt[s][t] = nc[s]; }
+    red[3 + kMaxSub][t] = rab;
+    red[4 + kMaxSub][t] = hab;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
-            for (int r = 0; r < 3 + kMaxSub; ++r) red[r][t] += red[r][t + w];
+            for (int r = 0; r < 5 + kMaxSub; ++r) red[r][t] += red[r][t + w];
             for (int s = 0; s < kMaxSub; ++s) cnt[s][t] += cnt[s][t + w];
         }
         __syncthreads();
@@ -240,6 +250,11 @@ __global__ __launch_bounds__(256) void k_derive_scalars(int32_t M, int32_t n_fix
         out[0] = Eff;
         out[1] = Eff + red[1][0] + 0.5 * red[2][0];
         for (int s = 0; s < S; ++s) phibar[s] = cnt[s][0] ? red[3 + s][0] / cnt[s][0] : 0.0;
+        const double B = dqmax * dqmax * red[3 + kMaxSub][0] + dqmax * red[4 + kMaxSub][0] + 1.0;
+        int ex = 0;
+        (void)frexp(B, &ex);   // B < 2^ex
+        out[2] = ldexp(1.0, 61 - ex);
+        out[3] = ldexp(1.0, ex - 61);
     }
 }
 
@@ -772,6 +787,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     if (M == 0 || M > 65535) return fail(ctx, GOAC_EINVAL, "problem_create: need 1..65535 mobile positions");
     const int32_t E = n_species;
     const int32_t Mp = (int32_t)round_up(M, kPad);
+    const int32_t Mq = (int32_t)round_up(M, 128);
     std::vector<uint8_t> msub(Mp, 0);
     std::vector<int32_t> tab(tab_words(S, E), 0);
     tab[0] = S;
@@ -831,6 +847,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     d.n = n;
     d.M = M;
     d.Mp = Mp;
+    d.Mq = Mq;
     d.S = S;
     d.E = E;
     d.mixed_exact = exact;
@@ -858,7 +875,7 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
                  o_c = ap.take(Mp * 8), o_q = ap.take(Mp * 8);
     const size_t up_end = ap.end;
     const size_t o_V64 = ap.take((size_t)M * Mp * 8), o_V32 = ap.take((size_t)M * Mp * 4),
-                 o_hi = ap.take((size_t)Mp * Mp * 2), o_lo = ap.take((size_t)Mp * Mp * 2), o_diag = ap.take(M * 8),
+                 o_hi = ap.take((size_t)Mq * Mq * 2), o_lo = ap.take((size_t)Mq * Mq * 2), o_diag = ap.take(M * 8),
                  o_rmax = ap.take(M * 4), o_rabs = ap.take(M * 8), o_h = ap.take(Mp * 8), o_ht = ap.take(Mp * 8),
                  o_pbar = ap.take(kMaxSub * 8), o_efix = ap.take((nf + 1) * 8), o_vc = ap.take(Mp * 8),
                  o_phi = ap.take(Mp * 8), o_out = ap.take(64);
@@ -914,16 +931,18 @@ extern "C" goac_status goac_problem_create(goac_ctx* ctx, const double* V, int64
     hipStream_t sm = ctx->stream;
     if (upload(ctx, base, img.data(), up_end) != GOAC_OK) return bail(GOAC_EHIP);
     {
-        const int64_t tot = (int64_t)Mp * Mp;
-        hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, sm, n, M, Mp, V, d.mob, d.V64,
-                           d.V32, d.Vhi, d.Vlo);
+        const int64_t tot = (int64_t)Mq * Mq;
+        hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, sm, n, M, Mp, Mq, V, d.mob,
+                           d.V64, d.V32, d.Vhi, d.Vlo);
         hipLaunchKernelGGL(k_rows, dim3((unsigned)((Mp + 3) / 4)), dim3(256), 0, sm, n, M, Mp, V, d.mob,
                            pb->fixed_idx, w_fq, nf, d.V64, w_c, w_q, d.diag, d.rowmax, d.rowabs, d.h, w_vc, w_phi);
         if (nf)
             hipLaunchKernelGGL(k_fixed_energy, dim3((unsigned)((nf + 3) / 4)), dim3(256), 0, sm, n, pb->fixed_idx,
                                w_fq, nf, V, w_efix);
+        double dqmax = 0.0;
+        for (double x : dq) dqmax = std::max(dqmax, std::fabs(x));
         hipLaunchKernelGGL(k_derive_scalars, dim3(1), dim3(256), 0, sm, M, nf, S, w_efix, w_c, d.h, w_vc, w_phi,
-                           d.msub, d.ht, d.phibar, w_out);
+                           d.msub, d.rowabs, dqmax, d.ht, d.phibar, w_out);
         if (hipGetLastError() != hipSuccess) {
             ctx->err = "problem_create: launch failed";
             return bail(GOAC_EHIP);
@@ -1000,12 +1019,20 @@ extern "C" goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t*
         return fail(ctx, GOAC_EINEXACT, "energies: a shifted charge is not bf16-exact");
     if (P == 0) return GOAC_OK;
     GOAC_HIP(ctx, hipSetDevice(ctx->device));
-    // The rows are checked first. The energy kernels are queued right behind the
-    // check and skip their work when it failed, so the host waits for the check
-    // alone while the device goes on without a gap; a rejected call leaves E as it was.
-    GOAC_TRY(rows_check_enqueue(pb, P, occ));
-    GOAC_TRY(prec == GOAC_MIXED ? energies_mixed(pb, P, occ, E, 0, ctx->chk_dev)
-                                : energies_fp64(pb, P, occ, E, ctx->chk_dev));
+    // The rows are checked first (the mixed path's row kernel checks them as it
+    // reads them). The energy kernels are queued right behind the check and skip
+    // their work when it failed, so the host waits for the check alone while the
+    // device goes on without a gap; a rejected call leaves E as it was.
+    if (prec == GOAC_MIXED) {
+        if (ctx->capturing) return fail(ctx, GOAC_EINVAL, "energies: row check inside a stream capture");
+        GOAC_TRY(check_buffers(ctx));
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ctx->chk_dev, 1);
+        GOAC_CHECK_LAUNCH(ctx);
+        GOAC_TRY(energies_mixed(pb, P, occ, E, 0, ctx->chk_dev, nullptr, ctx->chk_host, ctx->chk_ev));
+    } else {
+        GOAC_TRY(rows_check_enqueue(pb, P, occ));
+        GOAC_TRY(energies_fp64(pb, P, occ, E, ctx->chk_dev));
+    }
     return rows_check_wait(ctx, "energies");
 }
 

@@ -109,15 +109,16 @@ __host__ __device__ inline int tab_words(int S, int E) { return 2 + 2 * S + 2 * 
 struct ProblemDev {
     int64_t n;
     int32_t M, Mp, S, E;
+    int32_t Mq;          // M padded to the population product's 128-wide tiles
     int32_t* mob;        // M: site index of mobile position k (ascending)
     uint8_t* msub;       // Mp: sublattice of position k (0 beyond M)
     uint8_t* ref_occ;    // n: the problem's occupation (fixed-site species)
     int8_t* site_sub;    // n: site class of each site (-1 fixed)
     double* V64;         // M x Mp: mobile block, FP64 (zero beyond M)
     float* V32;          // M x Mp: FP32 rounding of V64
-    __hip_bfloat16* Vhi; // Mp x Mp: bf16(W), W = V block-lower-triangular with halved
+    __hip_bfloat16* Vhi; // Mq x Mq: bf16(W), W = V block-lower-triangular with halved
                          // diagonal 128 x 128 blocks (the population product's weights)
-    __hip_bfloat16* Vlo; // Mp x Mp: bf16(W - Vhi)
+    __hip_bfloat16* Vlo; // Mq x Mq: bf16(W - Vhi)
     double* diag;        // M
     float* rowmax;       // M: max_k |V_ik|, rounded up
     double* rowabs;      // M: sum_k |V_ik|
@@ -381,8 +382,13 @@ inline goac_status rows_check(goac_problem* pb, int64_t P, const uint8_t* occ, c
 // population energies (mixed bf16 hi+lo or FP64) and the k lowest of P energies
 // by (E, index); cnt_scratch holds P int32. With a gate, the kernels that read the
 // rows and write E do nothing while *gate is non-zero (rows a check rejected).
+// The mixed path takes chk (an int32, zero on entry) instead: its row kernel checks
+// the rows on the way and ors a broken row into *chk; the verdict is copied to *host
+// (pinned) when host is set and ev (when set) recorded right after that kernel; E is
+// left as it was when *chk is set.
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt = 0,
-                           const int32_t* gate = nullptr, WsSource* ws = nullptr);
+                           int32_t* chk = nullptr, WsSource* ws = nullptr, int32_t* host = nullptr,
+                           hipEvent_t ev = nullptr);
 goac_status energies_fp64(goac_problem* pb, int64_t P, const uint8_t* occ, double* E,
                           const int32_t* gate = nullptr, WsSource* ws = nullptr);
 // scratch bytes (with the 256-byte alignment of WsSource) that energies of P rows take

@@ -175,9 +175,13 @@ goac_status dgemm_nt(goac_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 // of them (stream-K: no partial last wave however the units fall). A share splits
 // into runs, one per (p-tile, j) it touches; a run accumulates its k-tiles on the
 // matrix cores (bf16 inputs, v_mfma_f32_32x32x16_bf16, FP32 accumulation) and its
-// fused epilogue writes the run's row sums sum_{n in j} dQ_pn Phi_pn (FP32 within
-// the tile, dQ a small integer) to part, the run's p-tile to run_mt. k_pop_finalize
-// adds a row's runs in a fixed order, so a given grid gives the same sums always.
+// fused epilogue adds the run's row sums sum_{n in j} dQ_pn Phi_pn (FP32 within the
+// tile, dQ a small integer) into the row's 64-bit fixed-point accumulator (scale
+// 2^sc, a power of two chosen per problem so that no sum of absolute terms of a row
+// reaches 2^61). Integer addition is associative, so the energies do not depend on
+// the order in which the runs finish (for a given grid, the same bits every call);
+// k_pop_finalize then writes E[p] = E~ + acc[p] / 2^sc.
+//
 // Tile 256 (p) x 128 (n) x 32 (k), 256 threads = 2 x 2 waves, each wave 128 x 64 =
 // 4 x 2 accumulators fed by the hi and the lo operand: 16 MFMAs per 8 LDS operand
 // reads. The next K stage is fetched into registers while the matrix cores work
@@ -190,8 +194,8 @@ static_assert(PB_BM * PB_DLD * 2 + PB_BM * 2 * 8 <= kPopLds, "epilogue staging e
 __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, const __hip_bfloat16* __restrict__ dQ,
                                                      const __hip_bfloat16* __restrict__ Vhi,
                                                      const __hip_bfloat16* __restrict__ Vlo,
-                                                     double* __restrict__ part, int32_t* __restrict__ run_mt,
-                                                     int32_t NT, int64_t U, int32_t G, int32_t R) {
+                                                     unsigned long long* __restrict__ rowacc, int32_t NT, int64_t U,
+                                                     int32_t G, const double* __restrict__ Ed) {
     // operand stages during the K loop; the epilogue reuses the same bytes for the
     // tile's dQ block and the row sums
     __shared__ __align__(16) unsigned char smem[kPopLds];
@@ -206,8 +210,8 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, cons
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    int r = 0;
-    for (int64_t u = U * g / G; u < u_end; ++r) {
+    const double scale = Ed[2];
+    for (int64_t u = U * g / G; u < u_end;) {
         // the run from unit u: p-tile mt, n-tile j, k-tiles i0 .. i0 + len - 1 of j
         const int mt = (int)(u / Umt);
         const int64_t rem = u - (int64_t)mt * Umt;
@@ -343,147 +347,155 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, cons
             }
         }
         __syncthreads();
-        const int64_t slot = (int64_t)g * R + r;
-        part[slot * PB_BM + tid] = red[tid][0] + red[tid][1];
-        if (tid == 0) run_mt[slot] = mt;
+        if (m0 + tid < P)
+            atomicAdd(rowacc + m0 + tid, (unsigned long long)__double2ll_rn((red[tid][0] + red[tid][1]) * scale));
         __syncthreads();   // the LDS is the next run's stage buffer
     }
-    for (; r < R; ++r)
-        if (tid == 0) run_mt[(int64_t)g * R + r] = -1;
 }
 
-// E[p] = E~ + lin[p] + the row sums of the runs on p's p-tile, with lin[p] =
-// sum_k dQ[p][k] ht[k] (FP64) from the row builder or, when it did not form it,
-// here: one wavefront per row, each lane sums its strided share in order, then a
-// fixed butterfly
-__global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, int32_t M, int32_t Mp, int32_t runs,
-                                                      const __hip_bfloat16* __restrict__ dQ,
-                                                      const double* __restrict__ ht, const double* __restrict__ part,
-                                                      const int32_t* __restrict__ run_mt,
-                                                      const double* __restrict__ lin, const double* __restrict__ Ed,
-                                                      double* __restrict__ E, const int32_t* __restrict__ gate) {
-    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+// E[p] = E~ + acc[p] / 2^sc, unless the gate is set
+__global__ __launch_bounds__(256) void k_pop_finalize(int64_t P, const long long* __restrict__ acc,
+                                                      const double* __restrict__ Ed, double* __restrict__ E,
+                                                      const int32_t* __restrict__ gate) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= P || (gate && *gate)) return;
-    const int mt = (int)(p / PB_BM), loc = (int)(p - (int64_t)mt * PB_BM);
-    double s = 0.0;
-    if (!lin)
-        for (int k = lane; k < M; k += 64) s += (double)__bfloat162float(dQ[p * Mp + k]) * ht[k];
-    for (int t = lane; t < runs; t += 64)
-        if (run_mt[t] == mt) s += part[(int64_t)t * PB_BM + loc];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) E[p] = Ed[1] + (lin ? lin[p] + s : s);
+    E[p] = Ed[1] + (double)acc[p] * Ed[3];
 }
 
-// dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M; grid (Mp/512, P),
-// 8 consecutive k per thread written as one 16-byte store
-__global__ void k_build_dq(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E, const uint8_t* __restrict__ occ,
-                           const int32_t* __restrict__ mob, const uint8_t* __restrict__ msub,
-                           const double* __restrict__ dq, __hip_bfloat16* __restrict__ out,
-                           const int32_t* __restrict__ gate) {
-    const int64_t p = blockIdx.y;
-    const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8;
-    if (k0 >= Mp || (gate && *gate)) return;
-    __hip_bfloat16 v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int k = k0 + q;
-        float x = 0.0f;
-        if (k < M) {
-            const int e = occ[p * n + mob[k]];
-            x = (float)dq[msub[k] * E + (e < E ? e : E - 1)];   // ids are checked; the clamp keeps reads in bounds
-        }
-        v[q] = __float2bfloat16(x);
-    }
-    *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
-}
+// Rows of the population product (Mq columns), one workgroup of T threads (64 to
+// 512) per row p, each thread taking 8 consecutive mobile positions per step:
+//   dQ[p][k] = bf16(charge[occ[p][mob[k]]] - c_{s(k)}), zero beyond M (16-byte stores);
+//   acc[p] = round(2^sc lin_p), lin_p = sum_k dQ[p][k] ht[k] in FP64 (each thread in
+//   order, then a fixed butterfly, then the waves in order).
+// With chk, the occupancy constraints of Eq. 2 are checked on the way: a species id
+// >= E, or (sublattice, species) counts over the row's mobile positions that differ
+// from the problem's, or 1 into *chk. With at most 16 (sublattice, species) pairs
+// the counts stay in registers, 8-bit fields of two 64-bit words moved to 32-bit
+// counters every 16 steps (before a field can pass 128); more pairs count in an LDS
+// histogram.
+constexpr int kPrepMaxT = 512;
 
-// The same for rows of at most kDqStageMax sites: one workgroup takes R rows, reads
-// them into LDS with coalesced 16-byte loads and gathers from LDS, reading the
-// position tables (site, sublattice, h~) once for the R rows. It also forms each
-// row's linear term lin[p] = sum_k dQ[p][k] ht[k] in FP64 (each thread sums its k
-// in order, then a fixed butterfly and the four waves in order).
-constexpr int64_t kDqStageMax = 48 * 1024;
-
-template <int R>
-__global__ __launch_bounds__(256) void k_build_dq_staged(int64_t P, int64_t n, int32_t M, int32_t Mp, int32_t E,
-                                                         const uint8_t* __restrict__ occ,
+__global__ __launch_bounds__(kPrepMaxT) void k_prep_rows(int64_t P, int64_t n, int32_t M, int32_t Mq, int32_t S,
+                                                         int32_t E, const uint8_t* __restrict__ occ,
                                                          const int32_t* __restrict__ mob,
                                                          const uint8_t* __restrict__ msub,
                                                          const double* __restrict__ dq,
                                                          const double* __restrict__ ht,
-                                                         __hip_bfloat16* __restrict__ out,
-                                                         double* __restrict__ lin,
-                                                         const int32_t* __restrict__ gate) {
-    extern __shared__ __align__(16) uint8_t rows[];
-    __shared__ double wsum[R][4];
-    if (gate && *gate) return;
-    const int64_t p0 = (int64_t)blockIdx.x * R;
-    const int64_t ld = round_up(n, 16);
+                                                         const int32_t* __restrict__ tab,
+                                                         const double* __restrict__ Ed,
+                                                         __hip_bfloat16* __restrict__ dQ,
+                                                         unsigned long long* __restrict__ acc,
+                                                         int32_t* __restrict__ chk) {
+    __shared__ int hist[kMaxSub * kMaxSpecies];
+    __shared__ double wsum[kPrepMaxT / 64];
+    const int64_t p = blockIdx.x;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int nb = S * E;
+    // loads off the row's dependency chain go out first
+    const double scale = Ed[2];
+    const int32_t* cnt = tab + 2 + 2 * S;
+    const int want = chk && tid < nb ? cnt[tid] : 0;
+    for (int x = tid; x < nb; x += T) hist[x] = 0;
+    if (chk && nb > 16) __syncthreads();   // the loop counts into the histogram
+    const uint8_t* row = occ + p * n;
+    double lin = 0.0;
+    bool bad = false;
+    uint32_t tot[16];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t p = p0 + r;
-        if (p >= P) break;
-        const uint8_t* src = occ + p * n;
-        uint8_t* row = rows + r * ld;
-        // rows start at p * n bytes: 16-byte loads only when that is aligned
-        if ((((uintptr_t)src) & 15) == 0) {
-            for (int64_t x = threadIdx.x * 16; x < n; x += 256 * 16) {
-                if (x + 16 <= n) *reinterpret_cast<uint4*>(row + x) = *reinterpret_cast<const uint4*>(src + x);
-                else
-                    for (int64_t y = x; y < n; ++y) row[y] = src[y];
+    for (int b = 0; b < 16; ++b) tot[b] = 0;
+    uint64_t lo = 0, hi = 0;
+    int steps = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            tot[b] += (uint32_t)((lo >> (8 * b)) & 0xffu);
+            tot[b + 8] += (uint32_t)((hi >> (8 * b)) & 0xffu);
+        }
+        lo = hi = 0;
+    };
+    for (int k0 = tid * 8; k0 < Mq; k0 += T * 8) {
+        int site[8];
+        uint2 sb = make_uint2(0, 0);
+        double h[8];
+        if (k0 + 8 <= M) {
+            const int4 a = *reinterpret_cast<const int4*>(mob + k0);
+            const int4 b = *reinterpret_cast<const int4*>(mob + k0 + 4);
+            site[0] = a.x; site[1] = a.y; site[2] = a.z; site[3] = a.w;
+            site[4] = b.x; site[5] = b.y; site[6] = b.z; site[7] = b.w;
+            sb = *reinterpret_cast<const uint2*>(msub + k0);
+#pragma unroll
+            for (int q = 0; q < 8; q += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(ht + k0 + q);
+                h[q] = t.x;
+                h[q + 1] = t.y;
             }
         } else {
-            for (int64_t x = threadIdx.x; x < n; x += 256) row[x] = src[x];
-        }
-    }
-    __syncthreads();
-    double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int k0 = threadIdx.x * 8; k0 < Mp; k0 += 256 * 8) {
-        // the position tables are read once for the R rows
-        int site[8], sub[8];
-        double h[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = k0 + q;
-            site[q] = k < M ? mob[k] : 0;
-            sub[q] = k < M ? msub[k] : 0;
-            h[q] = k < M ? ht[k] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t p = p0 + r;
-            if (p >= P) break;
-            const uint8_t* row = rows + r * ld;
-            __hip_bfloat16 v[8];
+            // the tail: the position tables hold M (mobile sites) and Mp entries
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int k = k0 + q;
-                double x = 0.0;
-                if (k < M) {
-                    const int e = row[site[q]];
-                    x = dq[sub[q] * E + (e < E ? e : E - 1)];   // ids are checked; the clamp keeps reads in bounds
-                    acc[r] += x * h[q];
-                }
-                v[q] = __float2bfloat16((float)x);
+                const bool in = k0 + q < M;
+                site[q] = in ? mob[k0 + q] : -1;
+                h[q] = in ? ht[k0 + q] : 0.0;
+                if (in) (q < 4 ? sb.x : sb.y) |= (uint32_t)msub[k0 + q] << (8 * (q & 3));
             }
-            *reinterpret_cast<uint4*>(out + p * Mp + k0) = *reinterpret_cast<const uint4*>(v);
+        }
+        __hip_bfloat16 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double x = 0.0;
+            if (site[q] >= 0) {
+                const int e = row[site[q]];
+                const int sl = (int)(((q < 4 ? sb.x : sb.y) >> (8 * (q & 3))) & 0xffu);
+                if (e >= E) {
+                    bad = true;
+                } else {
+                    const int b = sl * E + e;
+                    x = dq[b];
+                    if (nb <= 16) {
+                        lo += b < 8 ? 1ull << (8 * (b & 7)) : 0ull;
+                        hi += b >= 8 ? 1ull << (8 * (b & 7)) : 0ull;
+                    } else if (chk) {
+                        atomicAdd(&hist[b], 1);
+                    }
+                }
+                lin += x * h[q];
+            }
+            v[q] = __float2bfloat16((float)x);
+        }
+        *reinterpret_cast<uint4*>(dQ + p * Mq + k0) = *reinterpret_cast<const uint4*>(v);
+        if (nb <= 16 && ++steps == 16) {
+            flush();
+            steps = 0;
+        }
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    if (chk && nb <= 16) {
+        __syncthreads();   // the histogram is cleared
+        flush();
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (b < nb) {
+                uint32_t c = tot[b];
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) c += __shfl_xor(c, o, 64);
+                if (lane == 0) atomicAdd(&hist[b], (int)c);
+            }
         }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        double a = acc[r];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
-        if ((threadIdx.x & 63) == 0) wsum[r][threadIdx.x >> 6] = a;
-    }
+    for (int o = 1; o < 64; o <<= 1) lin += __shfl_xor(lin, o, 64);
+    if (lane == 0) wsum[wave] = lin;
     __syncthreads();
-    if (threadIdx.x < R && p0 + threadIdx.x < P)
-        lin[p0 + threadIdx.x] = ((wsum[threadIdx.x][0] + wsum[threadIdx.x][1]) + wsum[threadIdx.x][2]) +
-                                wsum[threadIdx.x][3];
+    if (tid == 0) {
+        double l = 0.0;
+        for (int w = 0; w < T / 64; ++w) l += wsum[w];
+        acc[p] = (unsigned long long)__double2ll_rn(l * scale);
+    }
+    if (!chk) return;
+    if (tid < nb && hist[tid] != want) bad = true;
+    for (int x = tid + T; x < nb; x += T)
+        if (hist[x] != cnt[x]) bad = true;
+    if (bad) atomicOr(chk, 1);
 }
 
 // Q[p][k] = charge[occ[p][mob[k]]] (FP64), zero beyond M
@@ -529,35 +541,18 @@ goac_status build_q64(goac_ctx* ctx, int64_t P, int64_t n, int32_t M, int32_t Mp
 }
 
 // Grid of the mixed product for P rows: U units (p-tile, n-tile j, k-tile i <= j)
-// shared by G workgroups, and R, the most runs one share splits into. G is the
-// number of units up to two workgroups per compute unit (more workgroups measured
-// faster at every population size tried), divided by the tile setting kt when one
-// is set or tuned.
+// shared by G workgroups. G is the number of units up to two workgroups per compute
+// unit (more workgroups measured faster at every population size tried), divided by
+// the tile setting kt when one is set or tuned. G moves the run boundaries, so the
+// energies differ between settings by the FP32 accumulation order only.
 struct PopPlan {
-    int32_t NT = 0, MT = 0, G = 0, R = 0;
+    int32_t NT = 0, MT = 0, G = 0;
     int64_t U = 0;
 };
 
-static int32_t pop_max_runs(int64_t U, int64_t Umt, int64_t G) {
-    int32_t R = 1;
-    for (int64_t g = 0; g < G; ++g) {
-        const int64_t u0 = U * g / G, u1 = U * (g + 1) / G;
-        int32_t r = 0;
-        for (int64_t u = u0; u < u1; ++r) {
-            const int64_t mt = u / Umt, rem = u - mt * Umt;
-            int64_t j = (int64_t)((std::sqrt(8.0 * (double)rem + 1.0) - 1.0) * 0.5);
-            while (j * (j + 1) / 2 > rem) --j;
-            while ((j + 1) * (j + 2) / 2 <= rem) ++j;
-            u += std::min<int64_t>(u1 - u, j + 1 - (rem - j * (j + 1) / 2));
-        }
-        R = std::max(R, r);
-    }
-    return R;
-}
-
 static PopPlan pop_plan(const goac_problem* pb, int64_t P, int32_t kt_req) {
     PopPlan pl;
-    pl.NT = (pb->d.Mp + PB_BN - 1) / PB_BN;
+    pl.NT = pb->d.Mq / PB_BN;
     pl.MT = (int32_t)((P + PB_BM - 1) / PB_BM);
     const int64_t Umt = (int64_t)pl.NT * (pl.NT + 1) / 2;
     pl.U = Umt * pl.MT;
@@ -567,69 +562,47 @@ static PopPlan pop_plan(const goac_problem* pb, int64_t P, int32_t kt_req) {
     }
     const int64_t slots = 2 * (int64_t)std::max(1, pb->ctx->num_cus);
     pl.G = (int32_t)std::min<int64_t>(pl.U, std::max<int64_t>(1, slots / kt_req));
-    pl.R = pop_max_runs(pl.U, Umt, pl.G);
     return pl;
+}
+
+// threads per row of the row kernel: 8 positions per thread and step, 64 to 512
+static int prep_threads(int32_t Mq) {
+    const int t = (int)std::min<int64_t>(kPrepMaxT, ((int64_t)Mq / 8 + 63) / 64 * 64);
+    return std::max(64, t);
 }
 
 size_t energies_scratch_bytes(const goac_problem* pb, int64_t P, goac_precision prec) {
     const ProblemDev& d = pb->d;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    if (prec == GOAC_MIXED) {
-        const PopPlan pl = pop_plan(pb, P, 0);
-        const size_t runs = (size_t)pl.G * pl.R;
-        const size_t dq_bytes = al((size_t)P * d.Mp * sizeof(__hip_bfloat16));
-        const size_t part_bytes = al(runs * PB_BM * sizeof(double));
-        const size_t mt_bytes = al(runs * sizeof(int32_t));
-        return al(dq_bytes + part_bytes + mt_bytes + (size_t)P * sizeof(double));
-    }
+    if (prec == GOAC_MIXED)
+        return al((size_t)P * d.Mq * sizeof(__hip_bfloat16)) + al((size_t)P * sizeof(long long));
     const size_t qb = al((size_t)P * d.Mp * sizeof(double));
     const int splits = dgemm_splits(pb->ctx, P, d.M, d.Mp, nullptr, false);
     return al(2 * qb) + (splits > 1 ? al((size_t)splits * P * d.M * sizeof(double)) : 0);
 }
 
 goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, double* E, int32_t kt_req,
-                           const int32_t* gate, WsSource* src) {
+                           int32_t* chk, WsSource* src, int32_t* host, hipEvent_t ev) {
     goac_ctx* ctx = pb->ctx;
     const ProblemDev& d = pb->d;
     const PopPlan pl = pop_plan(pb, P, kt_req);
-    const int64_t runs = (int64_t)pl.G * pl.R;
-    if (pl.U > ((int64_t)1 << 40) || runs > ((int64_t)1 << 30))
-        return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
-    const size_t dq_bytes = round_up((size_t)P * d.Mp * sizeof(__hip_bfloat16), 256);
-    const size_t part_bytes = round_up((size_t)runs * PB_BM * sizeof(double), 256);
-    const size_t mt_bytes = round_up((size_t)runs * sizeof(int32_t), 256);
+    if (pl.U > ((int64_t)1 << 40)) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
+    const size_t dq_bytes = round_up((size_t)P * d.Mq * sizeof(__hip_bfloat16), 256);
     WsSource own{ctx};
     void* ws = nullptr;
-    GOAC_TRY((src ? src : &own)->get(0, dq_bytes + part_bytes + mt_bytes + (size_t)P * sizeof(double), &ws));
+    GOAC_TRY((src ? src : &own)->get(0, dq_bytes + round_up((size_t)P * sizeof(long long), 256), &ws));
     __hip_bfloat16* dQ = (__hip_bfloat16*)ws;
-    double* part = (double*)((char*)ws + dq_bytes);
-    int32_t* run_mt = (int32_t*)((char*)ws + dq_bytes + part_bytes);
-    double* lin = nullptr;
-    if (d.n <= kDqStageMax) {
-        lin = (double*)((char*)ws + dq_bytes + part_bytes + mt_bytes);
-        // rows per workgroup: the position tables are read once for all of them
-        const int64_t ld = round_up(d.n, 16);
-        const int R = (P >= 4 * 2 * (int64_t)ctx->num_cus && 4 * ld <= 64 * 1024) ? 4
-                      : (P >= 2 * 2 * (int64_t)ctx->num_cus && 2 * ld <= 64 * 1024) ? 2 : 1;
-        const unsigned g = (unsigned)((P + R - 1) / R);
-        if (R == 4)
-            hipLaunchKernelGGL(k_build_dq_staged<4>, dim3(g), dim3(256), 4 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
-        else if (R == 2)
-            hipLaunchKernelGGL(k_build_dq_staged<2>, dim3(g), dim3(256), 2 * ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
-        else
-            hipLaunchKernelGGL(k_build_dq_staged<1>, dim3(g), dim3(256), ld, ctx->stream, P, d.n, d.M, d.Mp, d.E,
-                               occ, d.mob, d.msub, d.dq, d.ht, dQ, lin, gate);
-    } else
-        hipLaunchKernelGGL(k_build_dq, dim3((unsigned)((d.Mp + 511) / 512), (unsigned)P), dim3(64), 0, ctx->stream,
-                           P, d.n, d.M, d.Mp, d.E, occ, d.mob, d.msub, d.dq, dQ, gate);
+    unsigned long long* acc = (unsigned long long*)((char*)ws + dq_bytes);
+    hipLaunchKernelGGL(k_prep_rows, dim3((unsigned)P), dim3(prep_threads(d.Mq)), 0, ctx->stream, P, d.n, d.M, d.Mq,
+                       d.S, d.E, occ, d.mob, d.msub, d.dq, d.ht, d.tab, d.Ed, dQ, acc, chk);
     GOAC_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)pl.G), dim3(256), 0, ctx->stream, P, d.Mp, dQ, d.Vhi, d.Vlo, part,
-                       run_mt, pl.NT, pl.U, pl.G, pl.R);
+    if (host) GOAC_HIP(ctx, hipMemcpyAsync(host, chk, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    if (ev) GOAC_HIP(ctx, hipEventRecord(ev, ctx->stream));
+    hipLaunchKernelGGL(k_pop_bf16, dim3((unsigned)pl.G), dim3(256), 0, ctx->stream, P, d.Mq, dQ, d.Vhi, d.Vlo,
+                       acc, pl.NT, pl.U, pl.G, d.Ed);
     GOAC_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, ctx->stream, P, d.M, d.Mp,
-                       (int32_t)runs, dQ, d.ht, part, run_mt, lin, d.Ed, E, gate);
+    hipLaunchKernelGGL(k_pop_finalize, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, ctx->stream, P,
+                       (const long long*)acc, d.Ed, E, chk);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

@@ -34,6 +34,11 @@ hipError_t noalloc_setup(int device) {
     return hipSuccess;
 }
 
+// clears the check word
+__global__ void k_clear_flag(int32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
 static void* scratch_of(int device) {
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     return (device >= 0 && device < kNoAllocMaxDevices) ? g_scratch_ptr[device] : nullptr;
@@ -65,10 +70,16 @@ extern "C" goac_status goac_energies_noalloc(goac_problem* pb, int64_t P, const 
     int32_t* flag = (int32_t*)base;
     // the check (it clears the flag first), then the energy kernels, which skip all
     // work when the check failed
-    GOAC_TRY(rows_check_launch(pb, P, occ, flag));
     WsSource src{ctx, base + kNoAllocFlagBytes, kNoAllocScratchBytes - kNoAllocFlagBytes, 0};
-    GOAC_TRY(prec == GOAC_MIXED ? energies_mixed(pb, P, occ, E, 0, flag, &src)
-                                : energies_fp64(pb, P, occ, E, flag, &src));
+    if (prec == GOAC_MIXED) {
+        // the mixed path's row kernel checks the rows as it reads them
+        hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, ctx->stream, flag);
+        GOAC_CHECK_LAUNCH(ctx);
+        GOAC_TRY(energies_mixed(pb, P, occ, E, 0, flag, &src));
+    } else {
+        GOAC_TRY(rows_check_launch(pb, P, occ, flag));
+        GOAC_TRY(energies_fp64(pb, P, occ, E, flag, &src));
+    }
     int32_t bad = 0;
     GOAC_HIP(ctx, hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, ctx->stream));
     GOAC_HIP(ctx, hipStreamSynchronize(ctx->stream));

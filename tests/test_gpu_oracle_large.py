@@ -7,7 +7,8 @@ against the entry-by-entry matrix); the GPU builds its own with goac_build_ewald
 * Population energies (Eq. 2): mixed within 2e-5 eV per site of the oracle (the
   exact integer shift; an unshifted bf16 split is biased by about 1e-4) at every
   tile of the symmetric block schedule on the 8x8x8 cell with the GA's 1024 rows,
-  the 4x4x4 cell and the 16x16x8 cell with 512 rows; FP64 within 1e-6.
+  the 4x4x4 cell and the 16x16x8 cell with 512 rows; FP64 within 1e-6. The mixed
+  energies repeat bit-exactly for a grid setting.
 * Monte Carlo on cells of more than 1024 mobile positions, where the mixed field
   re-anchors between sweep chunks through the batched FP64 product: trajectories
   bit-exact against the oracle, with anchors taken over several chunks.
@@ -86,6 +87,29 @@ def test_energies_config3_every_tile_against_oracle(cfg3, kt):
     assert err.max() <= SHIFTED_MIXED, err.max()
     if kt == 1:
         assert _energy_errors(pb, cell, V, occ, rows, G.GOAC_FP64).max() <= TOL[0]
+
+
+@pytest.mark.parametrize("which", ["cfg3", "cfg5"])
+def test_energies_repeat_bit_exactly(request, which):
+    """The runs' row sums are added as 64-bit fixed-point integers, whose sum does
+    not depend on the order in which the runs finish: a grid setting gives the same
+    bits on every call. Settings differ only by where runs start their FP32
+    accumulation, far inside the mixed bound."""
+    cell, V, pb = request.getfixturevalue(which)
+    P = 1024 if which == "cfg3" else 512
+    occ = torch.from_numpy(S.random_occupations(cell, P, seed=9))
+    ref = None
+    try:
+        for kt in (1, 2, 4, 8):
+            pb.energies_tile(P, kt)
+            E = pb.energies(occ, G.GOAC_MIXED).cpu().numpy()
+            for _ in range(3):
+                assert np.array_equal(pb.energies(occ, G.GOAC_MIXED).cpu().numpy(), E), "tile %d" % kt
+            if ref is None:
+                ref = E
+            assert np.abs(E - ref).max() / len(cell["pos"]) <= 1e-6, "tile %d" % kt
+    finally:
+        pb.energies_tile(P, 0)
 
 
 def test_energies_config5_against_oracle(cfg5):
