@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--ga-generations", type=int, default=200)
     ap.add_argument("--only", default="", help="comma list of extra legs: fp64, energies, cfg1, cfg2, ga, cfg4, "
                                                 "nacl, gd, remc, hybrid (the step itself always runs)")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run the --only legs without the step and print their figures (for profiling)")
     return ap.parse_args()
 
 
@@ -148,6 +150,32 @@ def main():
               flush=True)
         return wall, tms, stats, Ek
 
+    def run_legs(result, legs):
+        if "energies" in legs:
+            result.update(energies_legs(ctx, G, S, torch, stream))
+        if "cfg1" in legs:
+            result.update(config1(ctx, G, S, torch, stream))
+        if "cfg2" in legs:
+            result.update(config2_step(ctx, G, S, torch, stream, max(2, args.steps)))
+        if "ga" in legs:
+            result.update(ga_energies(ctx, G, S, torch, stream, args.ga_generations))
+        if "cfg4" in legs:
+            result.update(batched_instances(ctx, G, S, torch, stream))
+        if "nacl" in legs:
+            result.update(nacl_half(ctx, G, S, torch, stream))
+        if "gd" in legs:
+            result.update(gradient_descent(ctx, G, S, torch, stream))
+        if "remc" in legs:
+            result.update(replica_exchange(ctx, G, S, torch, stream))
+        if "hybrid" in legs:
+            result.update(hybrid(ctx, G, S, torch, stream))
+
+    if args.legs_only:
+        legs = set(args.only.split(",")) - {""}
+        out = {"legs_only": sorted(legs)}
+        run_legs(out, legs)
+        print(json.dumps(out), flush=True)
+        return
     wall, tms, stats, Ek = timed(G.GOAC_MIXED, args.steps, args.warmup)
     value = float(C5) * T5 * args.steps / wall
     upd = float(stats["updates"].sum())
@@ -202,24 +230,7 @@ def main():
         result["plain_fp64_field_update_GBs"] = upd64 * 2.0 * M * 8.0 / result["plain_fp64_sweep_kernel_s"] / 1e9
         result["mixed_vs_fp64"] = result["value"] / result["plain_fp64_trials_per_s"]
         result["mixed_vs_fp64_sweep"] = result["plain_fp64_sweep_kernel_s"] / mc_s
-    if "energies" in legs:
-        result.update(energies_legs(ctx, G, S, torch, stream))
-    if "cfg1" in legs:
-        result.update(config1(ctx, G, S, torch, stream))
-    if "cfg2" in legs:
-        result.update(config2_step(ctx, G, S, torch, stream, max(2, args.steps)))
-    if "ga" in legs:
-        result.update(ga_energies(ctx, G, S, torch, stream, args.ga_generations))
-    if "cfg4" in legs:
-        result.update(batched_instances(ctx, G, S, torch, stream))
-    if "nacl" in legs:
-        result.update(nacl_half(ctx, G, S, torch, stream))
-    if "gd" in legs:
-        result.update(gradient_descent(ctx, G, S, torch, stream))
-    if "remc" in legs:
-        result.update(replica_exchange(ctx, G, S, torch, stream))
-    if "hybrid" in legs:
-        result.update(hybrid(ctx, G, S, torch, stream))
+    run_legs(result, legs)
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
