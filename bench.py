@@ -43,9 +43,9 @@ FP64_PEAK = 78.6e12
 # HBM bytes per k_mc<mixed, 256> launch of the step's sweep from FETCH_SIZE and
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of known
 # size; valid only for the kernel sources they were taken on
-MC_TRAFFIC = {"bytes": None,
+MC_TRAFFIC = {"bytes": 1.9682e11,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": ""}
+              "sha256": "196c4cbdea8da7eb1acf09ba9481df723d04b1dcd610e1bad7a3655609eff41a"}
 
 
 def parse():
