@@ -78,13 +78,16 @@ goac_status goac_ctx_synchronize(goac_ctx* ctx);
 /* Parameters of the Ewald split. A value <= 0 selects the default:
  * alpha = 5 / volume^(1/3) (1/A), rcut = 6 / alpha (A), and kmax = ceil(12 alpha
  * |a|_max / (2 pi)), the radius of the sphere of integer reciprocal indices
- * n1^2 + n2^2 + n3^2 <= kmax^2, n != 0. */
+ * n1^2 + n2^2 + n3^2 <= kmax^2, n != 0.
+ * flags: GOAC_EWALD_GENERAL sums every entry (no use of translation symmetry). */
 typedef struct {
     double alpha;
     double rcut;
     int32_t kmax;
-    int32_t reserved;
+    int32_t flags;
 } goac_ewald_params;
+
+#define GOAC_EWALD_GENERAL 1
 
 /* The periodic point-charge pair matrix (Methodology, "Cluster Expansion of
  * Coulomb Energy": Ewald summation of point charges, for which the second-order
@@ -95,6 +98,12 @@ typedef struct {
  * r = r_j - r_i, W the cell volume, G = n B, k_e = e/(4 pi eps0) (CODATA 2018),
  * tin-foil boundary, neutralising background kept in every entry, so that
  * E(q) = 1/2 q^T V q for any neutral q.
+ * V_ij depends on r_j - r_i only: when the sites are invariant under an
+ * axis-aligned grid of fractional translations (1/m0, 0, 0), (0, 1/m1, 0),
+ * (0, 0, 1/m2) (every supercell of a crystal is; each m the largest found), the
+ * sums run for one site per orbit of the grid and the other rows are those rows
+ * relabelled (equal to the full sum up to rounding); otherwise, or with
+ * GOAC_EWALD_GENERAL, every entry is summed.
  *   lattice_host : 9 doubles, rows are the lattice vectors (A)
  *   pos_host     : n x 3 Cartesian positions (A)
  *   V_dev        : n x n FP64 output, row-major, caller-owned

@@ -24,6 +24,7 @@ EDRIFT = -6
 TRACE_HASH = 1
 REMC_GRAPH = 2
 MC_TIMING = 4
+EWALD_GENERAL = 1
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTNEUTRAL", -5: "EINEXACT",
            -6: "EDRIFT", -7: "ESTATE"}
@@ -37,7 +38,7 @@ class GoacError(RuntimeError):
 
 
 class EwaldParams(C.Structure):
-    _fields_ = [("alpha", C.c_double), ("rcut", C.c_double), ("kmax", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("alpha", C.c_double), ("rcut", C.c_double), ("kmax", C.c_int32), ("flags", C.c_int32)]
 
 
 class ProblemInfo(C.Structure):
@@ -161,12 +162,13 @@ class Context:
     def synchronize(self):
         self.check(load().goac_ctx_synchronize(self._h))
 
-    def build_ewald(self, lattice, pos, alpha=0.0, rcut=0.0, kmax=0, out=None):
+    def build_ewald(self, lattice, pos, alpha=0.0, rcut=0.0, kmax=0, out=None, general=False):
+        """The n x n pair matrix; general=True sums every entry (GOAC_EWALD_GENERAL)."""
         lat = _np(lattice, np.float64).reshape(9)
         pos = _np(pos, np.float64)
         n = len(pos)
         V = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=self.device)
-        prm = EwaldParams(alpha, rcut, kmax, 0)
+        prm = EwaldParams(alpha, rcut, kmax, EWALD_GENERAL if general else 0)
         self.check(load().goac_build_ewald(self._h, lat.ctypes.data_as(C.c_void_p), n,
                                            pos.ctypes.data_as(C.c_void_p), C.byref(prm), _ptr(V)))
         return V

@@ -191,6 +191,15 @@ struct EwaldPlan {
     size_t b_frac = 0, b_pos = 0, b_tr = 0, b_G = 0, b_A = 0;
     int32_t K = 0, ld = 0, ntrans = 0;
     double alpha = 0.0, rcut = 0.0, ke = 0.0, cst = 0.0, self = 0.0;
+    int32_t flags_in = 0;
+    // translation symmetry of the sites: the grid Z_m0 x Z_m1 x Z_m2 of axis-aligned
+    // fractional translations that map the site set onto itself (nb = 0: none found).
+    // Site i is translate g_i of representative b_i; idx[b][g] is the site translate
+    // g of representative b. Uploaded after the general tables: reps (nb), site_b (n),
+    // site_g (n, packed), idx (n), int32 each.
+    int32_t nb = 0, ng = 0;
+    int32_t m[3] = {1, 1, 1};
+    size_t b_sym = 0;
 };
 
 struct goac_ctx {

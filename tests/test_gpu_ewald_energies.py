@@ -2,7 +2,8 @@
 starts and the top-k ranking against the FP64 oracle.
 
 Tolerances: V entries within 1e-12 of max|V| (both sides sum the same truncated
-series in FP64; only the order of additions differs); energies within 1e-6 eV
+series in FP64; only the order of additions differs, and on cells with
+translation symmetry the GPU sums one row per orbit); energies within 1e-6 eV
 per site (FP64 path) and 1e-4 eV per site (mixed path)."""
 import numpy as np
 import pytest
@@ -65,6 +66,41 @@ def test_ewald_general_cells(ctx, which):
     Vo = O.cell_matrix(cell)
     Vg = _gpu_V(ctx, cell).cpu().numpy()
     assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+
+
+def _random_cell(n, seed):
+    """n sites at random positions of a triclinic cell: no translation maps the set
+    onto itself, so the build sums every entry."""
+    rng = np.random.default_rng(seed)
+    lat = np.array([[9.0, 0.0, 0.0], [1.3, 8.2, 0.0], [0.7, -0.9, 10.1]])
+    pos = rng.random((n, 3)) @ lat
+    return lat, pos
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "nacl", "rocksalt_fcc", "spinel", "random"])
+def test_ewald_translation_rows_equal_the_full_sum(ctx, which):
+    """V_ij depends on r_j - r_i only: on a cell invariant under a grid of
+    translations the build sums one row per orbit and relabels it. That equals the
+    build that sums every entry (GOAC_EWALD_GENERAL) within the rounding of the
+    sums (1e-12 of max|V|): all-sites rock-salt cells (one orbit), an FCC rock-salt
+    cell (two), a spinel cell (fourteen), and random sites (no translation)."""
+    if which == "random":
+        lat, pos = _random_cell(200, 5)
+    else:
+        if which == "config1":
+            cell = S.config1()
+        elif which == "config2":
+            cell = S.config2()
+        elif which == "nacl":
+            cell = S.nacl_half()
+        else:
+            cells = S.config4(n_instances=8, seed=0, nmin=64, nmax=2048)
+            cell = cells[0] if which == "rocksalt_fcc" else cells[7]
+        lat, pos = cell["lattice"], cell["pos"]
+    Vs = ctx.build_ewald(lat, pos).cpu().numpy()
+    Vf = ctx.build_ewald(lat, pos, general=True).cpu().numpy()
+    assert np.abs(Vs - Vf).max() <= 1e-12 * np.abs(Vf).max()
+    assert np.array_equal(Vs, Vs.T) or np.abs(Vs - Vs.T).max() <= 1e-12 * np.abs(Vf).max()
 
 
 def test_ewald_alpha_choice_is_immaterial(ctx, cfg1):
