@@ -114,14 +114,6 @@ __device__ inline int64_t upper_bound_u64(const uint64_t* cum, int64_t P, uint64
 }
 
 // ------------------------------------------------------------------ GA: one child per wavefront
-constexpr int kInf = 0x7fffffff;
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // A wave's LDS operations complete in issue order, so ordering them across the
 // lanes of one wave needs no wait, only that the compiler keeps their order.
 __device__ __forceinline__ void wave_lds_order() {
@@ -129,154 +121,158 @@ __device__ __forceinline__ void wave_lds_order() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// first position >= from (in the sublattice's ascending list [0, len)) whose
-// predicate holds, scanning 64 at a time with a ballot; len if none
-template <typename Pred>
-__device__ inline int wave_find(int from, int len, Pred pred) {
-    const int lane = threadIdx.x & 63;
-    for (int base = from; base < len; base += 64) {
-        const int x = base + lane;
-        const bool hit = x < len && pred(x);
-        const uint64_t m = __ballot(hit);
-        if (m) return base + (int)__ffsll((long long)m) - 1;
-    }
-    return len;
-}
-
 // sublattices up to this length take the byte walk (crossover_bytes), longer ones
-// the row walk (crossover_rows) when its rows fit in LDS, else the scan walk
+// the window walk (crossover_win) over kWinWords words of 64 positions
 constexpr int kByteMaxLen = 1024;
+constexpr int kWinWords = 4;
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
 
-// Crossover walk of a sublattice with bit rows in LDS, one 64-bit word per 64
-// positions (nw words each): dis, the positions of the path copy ref that differ
-// from B; coin, the coin bit of every differing position (all drawn up front, 64
-// positions per ballot); and for each species e, hold[e], the positions holding e
-// in ref and differing from B. Every position before the walk's p agrees with B
-// in ref, so p's partner q is the first position of hold[B[p]].
-// The walk keeps its current window of 64 positions in registers: lane l holds
-// ref, B and the child at position 64 w + l, and lane e the window's word of
-// hold[e]. A step whose partner lies in the window reads and writes only those
-// registers (readlane / writelane with uniform indices); a partner further on is
-// found with 64-word ballots over LDS, where its updates go too. Leaving a window
-// writes its child bytes back (its ref and rows are no longer needed: every
-// position of it then agrees with B).
+// Crossover walk of a sublattice longer than the byte walk's range, through a
+// window of K consecutive 64-position words held in registers. Slot k holds word
+// w0 + k: lane l has the path copy's byte at position 64 (w0 + k) + l in rv[k]
+// and parent B's and the child's bytes (B | child << 8) in bc[k]; the uniform
+// masks cur[k] (the word's positions that still disagree with B and are not yet
+// walked) and cw[k] (the word's coins) sit in scalar registers. Every position
+// before the walk's p agrees with B, so p's partner q is the first position of
+// cur holding B[p] in the path copy: one compare and ballot per slot finds it,
+// and the swap is a few readlane / writelane with uniform lanes. A partner beyond
+// the window is found with 64-position ballots over the bytes in LDS, where its
+// update goes. When slot 0 has no position left, its child bytes return to LDS and
+// the window moves on by one word. coin: LDS for one 64-bit word per 64 positions.
 __device__ __forceinline__ uint32_t lane_get(uint32_t v, int l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
-__device__ void crossover_rows(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s, int E,
-                               uint64_t* rows, uint32_t c, uint32_t g, uint64_t seed, int lane) {
-    const int nw = (len + 63) >> 6;
-    uint64_t* dis = rows;
-    uint64_t* coin = rows + nw;
-    uint64_t* hold = rows + 2 * nw;
-    for (int x = lane; x < E * nw; x += 64) hold[x] = 0;
-    wave_lds_order();
-    for (int w = 0; w < nw; ++w) {
+// the writelane intrinsic (v_writelane_b32), which this compiler has no builtin for
+__device__ int amdgcn_writelane(int x, int l, int v) __asm("llvm.amdgcn.writelane.i32");
+
+// v with lane l (uniform) replaced by x (uniform)
+__device__ __forceinline__ uint32_t lane_put(uint32_t v, int l, uint32_t x) {
+    return (uint32_t)amdgcn_writelane((int)x, l, (int)v);
+}
+
+template <int K>
+struct WinWalk {
+    uint32_t rv[K], bc[K];
+    uint64_t cur[K], cw[K];
+    uint8_t* rs;
+    uint8_t* cs;
+    const uint8_t* bs;
+    const uint64_t* coin;
+    int len, nw, lane;
+
+    __device__ __forceinline__ void load(int k, int w) {
         const int x = w * 64 + lane;
-        const bool in = x < len;
-        const int a = in ? rs[x] : 0;
-        const bool d = in && a != bs[x];
-        const uint32_t sp = in ? (uint32_t)spos_s[x] : 0u;
-        const bool cn = d && (philox(sp, c, g, TAG_X, seed).x >> 31) != 0;
-        const uint64_t dm = __ballot(d), cm = __ballot(cn);
-        if (d) atomicOr(reinterpret_cast<unsigned long long*>(&hold[a * nw + w]), 1ull << lane);
-        if (lane == 0) {
-            dis[w] = dm;
-            coin[w] = cm;
-        }
+        const bool in = x < len;   // false for every w >= nw
+        const uint32_t r = in ? rs[x] : 0u, b = in ? bs[x] : 0u;
+        rv[k] = r;
+        bc[k] = b | ((in ? (uint32_t)cs[x] : 0u) << 8);
+        cur[k] = __ballot(r != b);
+        const uint64_t cwv = w < nw ? coin[w] : 0ull;
+        cw[k] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(cwv >> 32)) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)cwv);
     }
-    wave_lds_order();
-    int w = -1;
-    uint64_t cur = 0, cw = 0;
-    uint32_t rv = 0, bv = 0, cv = 0;   // the window: ref, B and the child at 64 w + lane
-    uint64_t hw = 0;                   // lane e: the window's word of hold[e]
-    for (;;) {
-        if (!cur) {
-            // leave the window (child bytes back to LDS), then find the next word
-            // with a differing position and load its window
-            if (w >= 0 && w * 64 + lane < len) cs[w * 64 + lane] = (uint8_t)cv;
-            int nxt = nw;
-            for (int base = w + 1; base < nw; base += 64) {
-                const int y = base + lane;
-                const uint64_t m = __ballot(y < nw && dis[y] != 0);
-                if (m) {
-                    nxt = base + (int)__ffsll((long long)m) - 1;
-                    break;
-                }
+
+    // p (slot 0, lane po, path byte a, packed B | child vp) swaps with the first
+    // holder of b = B[p] in slot k or later
+    template <int k>
+    __device__ __forceinline__ void swap(int po, uint32_t a, uint32_t vp, uint32_t take, int w0) {
+        const uint32_t b = vp & 0xffu;
+        if constexpr (k < K) {
+            const uint64_t hv = __ballot(rv[k] == b) & cur[k];
+            if (!hv) {
+                swap<k + 1>(po, a, vp, take, w0);
+                return;
             }
-            wave_lds_order();
-            if (nxt >= nw) break;
-            w = nxt;
-            const int x = w * 64 + lane;
-            const bool in = x < len;
-            rv = in ? rs[x] : 0u;
-            bv = in ? bs[x] : 0u;
-            cv = in ? cs[x] : 0u;
-            hw = lane < E ? hold[lane * nw + w] : 0ull;
-            cur = dis[w];
-            cw = coin[w];
-            wave_lds_order();
-        }
-        const int po = (int)__ffsll((long long)cur) - 1;
-        cur &= cur - 1;
-        const int a = (int)lane_get(rv, po);
-        const int b = (int)lane_get(bv, po);
-        const uint32_t cp = lane_get(cv, po);
-        const bool take = (cw >> po) & 1ull;   // the child takes this swap of the path
-        const uint64_t bitp = 1ull << po;
-        // partner: the first holder of b, in the window or further on
-        const uint64_t hv = readlane64(hw, b);
-        // p now agrees: it leaves hold[a]
-        hw = lane == a ? hw & ~bitp : hw;
-        if (hv) {
-            // in the window: registers only, no branches
             const int qo = (int)__ffsll((long long)hv) - 1;
-            const uint64_t bitq = 1ull << qo;
-            const int bq = (int)lane_get(bv, qo);
-            const uint32_t cq = lane_get(cv, qo);
-            const bool carry = bq != a;   // q keeps differing from B after taking a
-            hw = lane == b ? hw & ~bitq : hw;
-            hw = (carry && lane == a) ? hw | bitq : hw;
-            rv = (carry && lane == qo) ? (uint32_t)a : rv;
-            cur = carry ? cur : cur & ~bitq;
-            cv = (take && lane == po) ? cq : ((take && lane == qo) ? cp : cv);
+            const uint32_t vq = lane_get(bc[k], qo);
+            rv[k] = lane_put(rv[k], qo, a);
+            if ((vq & 0xffu) == a) cur[k] &= ~(1ull << qo);   // q now agrees with B
+            if (take) {
+                bc[0] = lane_put(bc[0], po, b | (vq & 0xff00u));
+                bc[k] = lane_put(bc[k], qo, (vq & 0xffu) | (vp & 0xff00u));
+            }
         } else {
-            int qw = nw;
-            uint64_t hq = 0;
-            const uint64_t* hb = hold + b * nw;
-            for (int base = w + 1; base < nw; base += 64) {
-                const int y = base + lane;
-                const uint64_t v = y < nw ? hb[y] : 0ull;
-                const uint64_t m = __ballot(v != 0);
+            // the partner lies beyond the window
+            for (int wb = w0 + K; wb < nw; ++wb) {
+                const int x = wb * 64 + lane;
+                const bool in = x < len;
+                const uint32_t r = in ? rs[x] : 0xffu, bb = in ? bs[x] : 0xffu;
+                const uint64_t m = __ballot(r == b && bb != b);
                 if (m) {
                     const int l = (int)__ffsll((long long)m) - 1;
-                    qw = base + l;
-                    hq = readlane64(v, l);
-                    break;
+                    const uint32_t cq = lane_get(in ? (uint32_t)cs[x] : 0u, l);
+                    if (lane == 0) {
+                        rs[wb * 64 + l] = (uint8_t)a;
+                        if (take) cs[wb * 64 + l] = (uint8_t)(vp >> 8);
+                    }
+                    if (take) bc[0] = lane_put(bc[0], po, b | (cq << 8));
+                    wave_lds_order();
+                    return;
                 }
             }
-            if (qw >= nw) break;   // cannot happen: ref and B share the composition
-            const int qo = (int)__ffsll((long long)hq) - 1;
-            const int q = qw * 64 + qo;
-            const int bq = bs[q];
-            const uint8_t cq = cs[q];
-            const bool carry = bq != a;
-            if (lane == 0) {
-                hold[b * nw + qw] = hq & ~(1ull << qo);
-                rs[q] = (uint8_t)a;
-                if (carry) atomicOr(reinterpret_cast<unsigned long long*>(&hold[a * nw + qw]), 1ull << qo);
-                else atomicAnd(reinterpret_cast<unsigned long long*>(&dis[qw]), ~(1ull << qo));
-                if (take) cs[q] = (uint8_t)cp;
-            }
-            cv = (take && lane == po) ? (uint32_t)cq : cv;
-            wave_lds_order();
+            // (no partner cannot happen: the path copy and B share the composition)
         }
     }
-    if (w >= 0 && w * 64 + lane < len) cs[w * 64 + lane] = (uint8_t)cv;   // (already written on the normal exit)
+
+    __device__ void run() {
+#pragma unroll
+        for (int k = 0; k < K; ++k) load(k, k);
+        int w0 = 0;
+        for (;;) {
+            while (cur[0]) {
+                const int po = (int)__ffsll((long long)cur[0]) - 1;
+                cur[0] &= cur[0] - 1;
+                const uint32_t a = lane_get(rv[0], po);
+                const uint32_t vp = lane_get(bc[0], po);
+                const uint32_t take = (uint32_t)(cw[0] >> po) & 1u;   // the child takes this swap of the path
+                swap<0>(po, a, vp, take, w0);
+            }
+            if (w0 * 64 + lane < len) cs[w0 * 64 + lane] = (uint8_t)(bc[0] >> 8);
+            if (++w0 >= nw) break;
+#pragma unroll
+            for (int k = 0; k + 1 < K; ++k) {
+                rv[k] = rv[k + 1];
+                bc[k] = bc[k + 1];
+                cur[k] = cur[k + 1];
+                cw[k] = cw[k + 1];
+            }
+            load(K - 1, w0 + K - 1);
+        }
+        wave_lds_order();
+    }
+};
+
+template <int K>
+__device__ void crossover_win(uint8_t* rs, uint8_t* cs, const uint8_t* bs, int len, const int32_t* spos_s,
+                              uint64_t* coin, uint32_t c, uint32_t g, uint64_t seed, int lane) {
+    const int nw = (len + 63) >> 6;
+    // the coin of every position, 64 per ballot, eight words' draws in flight together
+    for (int w8 = 0; w8 < nw; w8 += 8) {
+        uint32_t sp[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = (w8 + u) * 64 + lane;
+            sp[u] = x < len ? (uint32_t)spos_s[x] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = (w8 + u) * 64 + lane;
+            const uint64_t m = __ballot(x < len && (philox(sp[u], c, g, TAG_X, seed).x >> 31) != 0);
+            if (lane == 0 && w8 + u < nw) coin[w8 + u] = m;
+        }
+    }
     wave_lds_order();
+    WinWalk<K> ww;
+    ww.rs = rs;
+    ww.cs = cs;
+    ww.bs = bs;
+    ww.coin = coin;
+    ww.len = len;
+    ww.nw = nw;
+    ww.lane = lane;
+    ww.run();
 }
 
 // Crossover walk of one sublattice of at most 256 NR positions held in registers,
@@ -367,17 +363,15 @@ __device__ void crossover_bytes(uint8_t* cs, const uint8_t* bs, int len, const i
 //     each swap of the path iff the top bit of Philox(p_mobile, c, g, X) is set.
 //   mutation: with probability p_mut one valid swap, drawn as an MC proposal
 //     with the sublattice's positions ordered by (species, position).
-// Sublattices of up to 1024 positions take the byte walk (crossover_bytes); longer
-// ones the row walk (crossover_rows) when rows_words > 0 (the LDS of its rows, in
-// 64-bit words), else the scan walk, which finds p and q with 64-position ballots
-// over the path copy in LDS.
+// Sublattices of up to 1024 positions take the byte walk (crossover_bytes), longer
+// ones the window walk (crossover_win).
 __global__ __launch_bounds__(64) void k_ga_child(
     int64_t n, int32_t M, int32_t S, int32_t E, const int32_t* __restrict__ tab, const int32_t* __restrict__ spos,
     const int32_t* __restrict__ spos_inv, const uint8_t* __restrict__ msub, const int32_t* __restrict__ ssite,
     const int32_t* __restrict__ fixed_idx, int32_t n_fixed, const uint8_t* __restrict__ ref_occ, int64_t P,
     const uint8_t* __restrict__ pop_in, const uint64_t* __restrict__ cum, const int32_t* __restrict__ elite,
     int32_t n_elite, uint64_t seed, uint32_t g, const uint32_t* __restrict__ g_dev, double p_mut,
-    int32_t rows_words, uint8_t* __restrict__ pop_out) {
+    uint8_t* __restrict__ pop_out) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int64_t c = blockIdx.x;
     if (g_dev) g += *g_dev;   // a captured generation: the index is base + offset
@@ -407,12 +401,12 @@ __global__ __launch_bounds__(64) void k_ga_child(
         pb = upper_bound_u64(cum, P, mulhi64(xb, W));
     }
     // mobile occupations in sublattice order: ch (child), rf (path walk), bb (parent
-    // B); then the row walk's bit rows
+    // B); then the window walk's coin words
     const int Mr = (int)round_up(M, 16);
     uint8_t* ch = lds;
     uint8_t* rf = lds + Mr;
     uint8_t* bb = lds + 2 * Mr;
-    uint64_t* rows = reinterpret_cast<uint64_t*>(lds + round_up(3 * (int64_t)Mr, 16));
+    uint64_t* coin = reinterpret_cast<uint64_t*>(lds + round_up(3 * (int64_t)Mr, 16));
     const uint8_t* A = pop_in + pa * n;
     const uint8_t* B = pop_in + pb * n;
     // eight positions per lane per round, their loads in flight together
@@ -448,27 +442,7 @@ __global__ __launch_bounds__(64) void k_ga_child(
             else crossover_bytes<4>(cs, bs, len, spos + base, (uint32_t)c, g, seed, lane);
             continue;
         }
-        if ((int64_t)(E + 2) * ((len + 63) / 64) <= rows_words) {
-            crossover_rows(rs, cs, bs, len, spos + base, E, rows, (uint32_t)c, g, seed, lane);
-            continue;
-        }
-        // scan walk: the next disagreeing position and its partner, 64 positions at a
-        // time; lane 0 swaps the path copy and, on a set coin, the child
-        int p = 0;
-        for (;;) {
-            p = wave_find(p, len, [&](int x) { return rs[x] != bs[x]; });
-            if (p >= len) break;
-            const uint8_t want = bs[p];
-            const int q = wave_find(p + 1, len, [&](int x) { return rs[x] == want && rs[x] != bs[x]; });
-            if (q >= len) break;  // cannot happen: ref and B share the composition
-            if (lane == 0) {
-                const uint8_t t = rs[p]; rs[p] = rs[q]; rs[q] = t;
-                const u32x4 rx = philox((uint32_t)spos[base + p], (uint32_t)c, g, TAG_X, seed);
-                if (rx.x >> 31) { const uint8_t t2 = cs[p]; cs[p] = cs[q]; cs[q] = t2; }
-            }
-            wave_lds_order();
-            ++p;
-        }
+        crossover_win<kWinWords>(rs, cs, bs, len, spos + base, coin, (uint32_t)c, g, seed, lane);
     }
     // mutation: one valid swap with probability p_mut
     const u32x4 rm = philox((uint32_t)c, g, 1u, TAG_MUT, seed);
@@ -519,21 +493,14 @@ __global__ __launch_bounds__(64) void k_ga_child(
     for (int f = lane; f < n_fixed; f += 64) out[fixed_idx[f]] = ref_occ[fixed_idx[f]];
 }
 
-// LDS of a child: its occupation, the path copy and parent B (bytes), then the row
-// walk's bit rows for the longest sublattice above the byte walk's range: (E + 2)
-// words per 64 positions, left out when they would not fit (those sublattices then
-// take the scan walk)
-static int64_t ga_rows_words(const goac_problem* pb) {
+// LDS of a child: its occupation, the path copy and parent B (bytes), then the
+// window walk's coin words (one per 64 positions of the longest sublattice above
+// the byte walk's range)
+size_t ga_child_lds(const goac_problem* pb) {
     int maxlen = 0;
     for (int s = 0; s < pb->d.S; ++s) maxlen = std::max(maxlen, (int)pb->tab_host[2 + s]);
-    if (maxlen <= kByteMaxLen) return 0;
-    const int64_t words = (int64_t)(pb->d.E + 2) * ((maxlen + 63) / 64);
-    const int64_t base = round_up(3 * round_up(pb->d.M, 16), 16);
-    return base + 8 * words <= 160 * 1024 ? words : 0;
-}
-
-size_t ga_child_lds(const goac_problem* pb) {
-    return round_up(3 * round_up(pb->d.M, 16), 16) + 8 * ga_rows_words(pb);
+    const int64_t words = maxlen > kByteMaxLen ? (maxlen + 63) / 64 : 0;
+    return round_up(3 * round_up(pb->d.M, 16), 16) + 8 * words;
 }
 
 goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, const uint64_t* cum, const int32_t* elite,
@@ -545,7 +512,7 @@ goac_status ga_children(goac_problem* pb, int64_t P, const uint8_t* pop_in, cons
         GOAC_HIP(ctx, hipFuncSetAttribute((const void*)k_ga_child, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_ga_child, dim3((unsigned)P), dim3(64), lds, ctx->stream, d.n, d.M, d.S, d.E, d.tab, pb->spos,
                        pb->spos_inv, d.msub, pb->ssite, pb->fixed_idx, pb->n_fixed, d.ref_occ, P, pop_in, cum, elite,
-                       n_elite, prm->seed, prm->generation, g_dev, prm->p_mut, (int32_t)ga_rows_words(pb), pop_out);
+                       n_elite, prm->seed, prm->generation, g_dev, prm->p_mut, pop_out);
     GOAC_CHECK_LAUNCH(ctx);
     return GOAC_OK;
 }

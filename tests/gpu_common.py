@@ -56,3 +56,43 @@ def degenerate_sublattice_cell():
     spc[cat[:8]] = 3
     spc[cat[8:]] = np.array([1, 2] * 4, np.uint8)
     return S.make_cell(lat, pos, sub, spc, charge, names)
+
+
+def long_window_cell(seed=5):
+    """3072 sites of a 16x16x12 simple-cubic grid (a = 3 A) in seeded random site
+    order: sublattice 0 has 1500 positions (23 words of 64 and a 28-position tail)
+    holding 24 species with counts from 1 to 300, so that some partners lie many
+    words ahead; sublattice 1 has 1100 positions holding four species; 472 sites
+    are fixed. The pair matrix is not used, so the charges are placeholders."""
+    g = np.stack(np.meshgrid(np.arange(16), np.arange(16), np.arange(12), indexing="ij"), -1).reshape(-1, 3)
+    lat = np.diag([48.0, 48.0, 36.0])
+    pos = g * 3.0
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = rng.permutation(len(pos))
+    sub = np.full(len(pos), -1, np.int32)
+    sub[order[:1500]] = 0
+    sub[order[1500:2600]] = 1
+    small = [1, 1, 2, 3, 5, 8, 13, 21, 34, 55] + [25] * 9 + [32]
+    counts0 = [300, 300, 250, 250] + small
+    assert sum(counts0) == 1500 and len(counts0) == 24
+    spc = np.full(len(pos), 28, np.uint8)
+    spc[order[:1500]] = np.repeat(np.arange(24), counts0).astype(np.uint8)
+    spc[order[1500:2600]] = np.repeat(np.arange(24, 28), [500, 300, 200, 100]).astype(np.uint8)
+    names = ["X%d" % e for e in range(29)]
+    return S.make_cell(lat, pos, sub, spc, [0.0] * 29, names)
+
+
+def near_copies(cell, P, swaps, seed):
+    """P occupations that each differ from one seeded random occupation by up to
+    `swaps` random exchanges inside the mobile sublattices (parents that agree on
+    most 64-position words)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = S.random_occupations(cell, 1, seed)[0]
+    out = np.repeat(base[None, :], P, axis=0)
+    subs = sorted(set(cell["sublattice"].tolist()) - {-1})
+    for p in range(P):
+        for _ in range(int(rng.integers(0, swaps + 1))):
+            idx = np.nonzero(cell["sublattice"] == subs[int(rng.integers(len(subs)))])[0]
+            i, j = rng.choice(idx, 2, replace=False)
+            out[p, i], out[p, j] = out[p, j], out[p, i]
+    return out

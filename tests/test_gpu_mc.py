@@ -10,7 +10,8 @@ import torch
 
 import oracle as O
 import supercells as S
-from gpu_common import degenerate_sublattice_cell, many_species_cell, two_sublattice_cell
+from gpu_common import (degenerate_sublattice_cell, long_window_cell, many_species_cell, near_copies,
+                        two_sublattice_cell)
 
 pytestmark = pytest.mark.gpu
 
@@ -513,9 +514,9 @@ def test_ga_generation_reports_roulette_overflow(ctx, cfg1):
 @pytest.mark.parametrize("which,P", [("config1", 64), ("config2", 203), ("config3", 1024), ("two", 96),
                                      ("config5", 24), ("many", 40)])
 def test_ga_generation_bitexact(ctx, which, P):
-    """Covers the register-resident crossover walk (sublattices of up to 4096
-    positions, up to 16 species) and the LDS walk (the 8192-position sublattice of
-    the 16384-site cell; the 20-species cell)."""
+    """Covers the byte walk (sublattices of up to 1024 positions, up to 20 species)
+    and the window walk (the 2048-position sublattice of the 8x8x8 cell, the
+    8192-position sublattice of the 16384-site cell)."""
     cell = {"two": two_sublattice_cell, "many": many_species_cell}.get(which, getattr(S, which, None))()
     V = torch.zeros((len(cell["pos"]),) * 2, dtype=torch.float64)
     pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
@@ -532,6 +533,25 @@ def test_ga_generation_bitexact(ctx, which, P):
     got = pb.ga_generation(torch.from_numpy(pop), torch.zeros(P, dtype=torch.float64), seed=3, generation=9,
                            n_elite=2, p_mut=0.5).cpu().numpy()
     assert np.array_equal(got, O.ga_generation(cell, pop, np.zeros(P), seed=3, g=9, n_elite=2, p_mut=0.5))
+
+
+@pytest.mark.parametrize("parents", ["random", "near"])
+def test_ga_window_walk_bitexact(ctx, parents):
+    """The window walk on two long sublattices (1500 positions with a 28-position
+    tail and 24 species, some with one or two ions, whose partners lie words ahead
+    of the window; 1100 positions with four species), from random parents and from
+    parents that agree on most words."""
+    cell = long_window_cell()
+    P = 96
+    V = torch.zeros((len(cell["pos"]),) * 2, dtype=torch.float64)
+    pb = G.Problem(ctx, V, cell["sublattice"], cell["species"], cell["charge"])
+    pop = O.init_occupations(cell, P, seed=2) if parents == "random" else near_copies(cell, P, 40, seed=4)
+    E = -10.0 + np.random.default_rng(11).normal(0.0, 1.0, P)
+    for g, (ne, pm) in enumerate([(4, 0.3), (0, 0.0)]):
+        got = pb.ga_generation(torch.from_numpy(pop), torch.from_numpy(E), seed=17, generation=g, n_elite=ne,
+                               p_mut=pm).cpu().numpy()
+        assert np.array_equal(got, O.ga_generation(cell, pop, E, seed=17, g=g, n_elite=ne, p_mut=pm))
+    pb.close()
 
 
 def test_ga_weight_overflow_is_an_error(ctx, cfg1):
