@@ -124,7 +124,7 @@ __device__ __forceinline__ void wave_lds_order() {
 // sublattices up to this length take the byte walk (crossover_bytes), longer ones
 // the window walk (crossover_win) over kWinWords words of 64 positions
 constexpr int kByteMaxLen = 1024;
-constexpr int kWinWords = 4;
+constexpr int kWinWords = 3;
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
 
