@@ -47,9 +47,9 @@ FP64_PEAK = 78.6e12
 # and 8192 the fastest sweep (fewer batched anchors against more exact fallbacks;
 # the decisions, hence the trajectories, are the same for any interval)
 REANCHOR5 = 2048
-MC_TRAFFIC = {"bytes": 1.9682e11,
+MC_TRAFFIC = {"bytes": 3.7804e11,
               "sources": ("paper_2409_08808_amd/csrc/mc.hip", "paper_2409_08808_amd/csrc/common.h"),
-              "sha256": "196c4cbdea8da7eb1acf09ba9481df723d04b1dcd610e1bad7a3655609eff41a"}
+              "sha256": "5e1d376904bf237eb4dd30eedd326f699704660735d45650b20a655691edf7cb"}
 
 
 def parse():
