@@ -188,8 +188,9 @@ goac_status goac_energies(goac_problem* pb, int64_t P, const uint8_t* occ_dev,
  * every GPU the library runs on holds until the process ends. No device or pinned
  * memory is allocated. The call waits for the stream (it reads the row check back
  * into host memory of its own stack).
- *   Limit: the energies of P rows must fit the array (about P x (M x 2 + 8) bytes
- *   for GOAC_MIXED, P x M x 16 bytes plus split-K partials for GOAC_FP64);
+ *   Limit: the energies of P rows must fit the array (about P' x M x 2 + P x 8
+ *   bytes for GOAC_MIXED, P' = P rounded up to a multiple of 256; P x M x 16 bytes
+ *   plus split-K partials for GOAC_FP64);
  *   larger calls return EINVAL and compute nothing.
  *   Concurrency: all calls on one GPU share its array, which keeps the last call's
  *   contents; calls that overlap on one GPU (other host threads, other streams)

@@ -14,6 +14,7 @@ namespace goac {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ FP64 NT GEMM
 // C = alpha A B^T + beta C, A: M x K (lda), B: N x K (ldb), FP64.
@@ -232,39 +233,36 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, cons
             for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
         // loader: the p-tile is 256 rows x 32 k = 1024 chunks of 8 bf16 (four per
         // thread), each n-tile 128 rows x 32 k (two per thread)
-        uint4 ra[4], rh[2], rl[2];
+        // Thread tid loads rows tid / 4 + 64 q at columns 8 (tid % 4) of each operand;
+        // dQ and W share the row stride Mp, so one 32-bit element offset serves every
+        // load beside a uniform base. dQ has rows up to the next multiple of 256 and W
+        // is Mq x Mq, so every load lies inside its buffer and none is conditional.
+        v4u32 ra[4], rh[2], rl[2];
+        const uint32_t to = (uint32_t)(tid >> 2) * (uint32_t)Mp + (uint32_t)(tid & 3) * 8u;
+        const int64_t slab = (int64_t)64 * Mp;
         auto fetch = [&](int k0) {
+            const __hip_bfloat16* a0 = dQ + m0 * Mp + k0;
+            const __hip_bfloat16* h0 = Vhi + (int64_t)n0 * Mp + k0;
+            const __hip_bfloat16* l0 = Vlo + (int64_t)n0 * Mp + k0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int idx = tid + q * 256;
-                const int rr = idx >> 2;
-                const int c = (idx & 3) * 8;
-                const int64_t gp = m0 + rr;
-                ra[q] = gp < P ? *reinterpret_cast<const uint4*>(dQ + gp * Mp + k0 + c) : make_uint4(0, 0, 0, 0);
-            }
+            for (int q = 0; q < 4; ++q) ra[q] = *reinterpret_cast<const v4u32*>(a0 + q * slab + to);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const int idx = tid + q * 256;
-                const int rr = idx >> 2;
-                const int c = (idx & 3) * 8;
-                const int gn = n0 + rr;
-                rh[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vhi + (int64_t)gn * Mp + k0 + c)
-                                : make_uint4(0, 0, 0, 0);
-                rl[q] = gn < Mp ? *reinterpret_cast<const uint4*>(Vlo + (int64_t)gn * Mp + k0 + c)
-                                : make_uint4(0, 0, 0, 0);
+                rh[q] = *reinterpret_cast<const v4u32*>(h0 + q * slab + to);
+                rl[q] = *reinterpret_cast<const v4u32*>(l0 + q * slab + to);
             }
         };
         auto stash = [&](int buf) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int idx = tid + q * 256;
-                *reinterpret_cast<uint4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
+                *reinterpret_cast<v4u32*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int idx = tid + q * 256;
-                *reinterpret_cast<uint4*>(&Hs[buf][idx >> 2][(idx & 3) * 8]) = rh[q];
-                *reinterpret_cast<uint4*>(&Ls[buf][idx >> 2][(idx & 3) * 8]) = rl[q];
+                *reinterpret_cast<v4u32*>(&Hs[buf][idx >> 2][(idx & 3) * 8]) = rh[q];
+                *reinterpret_cast<v4u32*>(&Ls[buf][idx >> 2][(idx & 3) * 8]) = rl[q];
             }
         };
         fetch(kbeg);
@@ -308,12 +306,13 @@ __global__ __launch_bounds__(256, 2) void k_pop_bf16(int64_t P, int32_t Mp, cons
         // its half (masks 16, 8, 4, 2, 1, each step keeping half of the rows) leaves
         // row v(lane) summed over all 32 columns in lanes 2c and 2c + 1 (fixed order,
         // deterministic).
-        for (int x = tid; x < PB_BM * (PB_BN / 8); x += 256) {
-            const int rr = x / (PB_BN / 8), c = (x % (PB_BN / 8)) * 8;
-            const int64_t gp = m0 + rr;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gp < P && n0 + c < Mp) v = *reinterpret_cast<const uint4*>(dQ + gp * Mp + n0 + c);
-            *reinterpret_cast<uint4*>(&Ds[rr][c]) = v;
+        {
+            const __hip_bfloat16* d0 = dQ + m0 * Mp + n0;
+            for (int x = tid; x < PB_BM * (PB_BN / 8); x += 256) {
+                const int rr = x / (PB_BN / 8), c = (x % (PB_BN / 8)) * 8;
+                *reinterpret_cast<uint4*>(&Ds[rr][c]) =
+                    *reinterpret_cast<const uint4*>(d0 + ((uint32_t)rr * (uint32_t)Mp + (uint32_t)c));
+            }
         }
         __syncthreads();
         const int c32 = lane & 31, h = lane >> 5;
@@ -575,7 +574,7 @@ size_t energies_scratch_bytes(const goac_problem* pb, int64_t P, goac_precision 
     const ProblemDev& d = pb->d;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     if (prec == GOAC_MIXED)
-        return al((size_t)P * d.Mq * sizeof(__hip_bfloat16)) + al((size_t)P * sizeof(long long));
+        return al((size_t)round_up(P, PB_BM) * d.Mq * sizeof(__hip_bfloat16)) + al((size_t)P * sizeof(long long));
     const size_t qb = al((size_t)P * d.Mp * sizeof(double));
     const int splits = dgemm_splits(pb->ctx, P, d.M, d.Mp, nullptr, false);
     return al(2 * qb) + (splits > 1 ? al((size_t)splits * P * d.M * sizeof(double)) : 0);
@@ -587,7 +586,9 @@ goac_status energies_mixed(goac_problem* pb, int64_t P, const uint8_t* occ, doub
     const ProblemDev& d = pb->d;
     const PopPlan pl = pop_plan(pb, P, kt_req);
     if (pl.U > ((int64_t)1 << 40)) return fail(ctx, GOAC_EINVAL, "energies: population too large for one launch");
-    const size_t dq_bytes = round_up((size_t)P * d.Mq * sizeof(__hip_bfloat16), 256);
+    // dQ rows up to the product's next p-tile boundary (the rows past P are read,
+    // never written, and only feed product rows that are discarded)
+    const size_t dq_bytes = round_up((size_t)round_up(P, PB_BM) * d.Mq * sizeof(__hip_bfloat16), 256);
     WsSource own{ctx};
     void* ws = nullptr;
     GOAC_TRY((src ? src : &own)->get(0, dq_bytes + round_up((size_t)P * sizeof(long long), 256), &ws));
