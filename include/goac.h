@@ -394,7 +394,7 @@ typedef struct {
  * them, and pop_out_dev is then left untouched. EINVAL also when a child's mobile
  * positions do not fit one workgroup's LDS (3 bytes per mobile position plus one
  * 8-byte word per 64 positions of the longest sublattice, at most 160 KiB: about
- * 53,000 mobile positions). */
+ * 52,000 mobile positions). */
 goac_status goac_ga_generation(goac_problem* pb, int64_t P, const uint8_t* pop_in_dev,
                                const double* E_in_dev, const goac_ga_params* params,
                                uint8_t* pop_out_dev);
