@@ -100,10 +100,11 @@ typedef struct {
  * E(q) = 1/2 q^T V q for any neutral q.
  * V_ij depends on r_j - r_i only: when the sites are invariant under an
  * axis-aligned grid of fractional translations (1/m0, 0, 0), (0, 1/m1, 0),
- * (0, 0, 1/m2) (every supercell of a crystal is; each m the largest found), the
- * sums run for one site per orbit of the grid and the other rows are those rows
- * relabelled (equal to the full sum up to rounding); otherwise, or with
- * GOAC_EWALD_GENERAL, every entry is summed.
+ * (0, 0, 1/m2) (every supercell of a crystal is; each m the largest found; sites
+ * match when their fractional coordinates agree within 1e-10), the sums run for
+ * one site per orbit of the grid and the other rows are those rows relabelled
+ * (equal to the full sum up to rounding); otherwise, or with GOAC_EWALD_GENERAL,
+ * every entry is summed.
  *   lattice_host : 9 doubles, rows are the lattice vectors (A)
  *   pos_host     : n x 3 Cartesian positions (A)
  *   V_dev        : n x n FP64 output, row-major, caller-owned

@@ -172,10 +172,12 @@ __global__ void k_ewald_table(int64_t n, int32_t K, int32_t ld, const double* __
 // The grid of axis-aligned fractional translations (1/m0, 0, 0), (0, 1/m1, 0),
 // (0, 0, 1/m2) under which the site set is invariant, with each axis's m the largest
 // that works, and each site's representative and translate (nb = 0 when the grid is
-// trivial or anything does not add up). Positions are matched on a 2^-20 grid of
-// fractional coordinates, each lookup trying the neighbouring keys too, so a site
-// displaced by rounding is still found; a set that is not a translate of itself
-// fails and the general build is used.
+// trivial or anything does not add up). Positions are hashed on a 2^-20 grid of
+// fractional coordinates, each lookup trying the neighbouring keys too, and a match
+// must agree within kSymTol in every fractional coordinate: sites that differ by the
+// rounding of their coordinates match, a set perturbed by more (noise in the
+// input) is not a translate of itself and takes the general build.
+constexpr double kSymTol = 1e-10;
 static void ewald_symmetry(const std::vector<double>& frac, int64_t n, EwaldPlan& P, std::vector<int32_t>& sym) {
     P.nb = 0;
     P.ng = 0;
@@ -195,7 +197,12 @@ static void ewald_symmetry(const std::vector<double>& frac, int64_t n, EwaldPlan
             for (int db = -1; db <= 1; ++db)
                 for (int dc = -1; dc <= 1; ++dc) {
                     const auto it = at.find(key((a + da) & (Q - 1), (b + db) & (Q - 1), (c + dc) & (Q - 1)));
-                    if (it != at.end()) return it->second;
+                    if (it == at.end()) continue;
+                    const int64_t r = it->second;
+                    const double e[3] = {frac[3 * r] - f0, frac[3 * r + 1] - f1, frac[3 * r + 2] - f2};
+                    bool close = true;
+                    for (int d = 0; d < 3; ++d) close = close && std::fabs(e[d] - std::nearbyint(e[d])) <= kSymTol;
+                    if (close) return (int32_t)r;
                 }
         return -1;
     };

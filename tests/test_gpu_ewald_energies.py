@@ -103,6 +103,26 @@ def test_ewald_translation_rows_equal_the_full_sum(ctx, which):
     assert np.array_equal(Vs, Vs.T) or np.abs(Vs - Vs.T).max() <= 1e-12 * np.abs(Vf).max()
 
 
+@pytest.mark.parametrize("noise", [1e-12, 1e-6])
+def test_ewald_noisy_positions(ctx, noise):
+    """Sites displaced by rounding-sized amounts (1e-12 A) still count as a grid
+    translate of each other and take the orbit build, which then uses the
+    representatives' positions: each entry may move by up to |grad V| times the
+    two sites' displacements, |grad V| <= k_e / r^2 = 3.3 eV/A at the 2.1 A nearest
+    distance (the bound below takes 20 eV/A per A of noise, plus 1e-12 of max|V|
+    for the sums' rounding). Sites displaced by 1e-6 A are not translates, and the
+    build sums every entry (bit-identical to GOAC_EWALD_GENERAL)."""
+    cell = S.config2()
+    rng = np.random.default_rng(3)
+    pos = cell["pos"] + rng.uniform(-noise, noise, cell["pos"].shape)
+    Vs = ctx.build_ewald(cell["lattice"], pos).cpu().numpy()
+    Vf = ctx.build_ewald(cell["lattice"], pos, general=True).cpu().numpy()
+    if noise < 1e-9:
+        assert np.abs(Vs - Vf).max() <= 1e-12 * np.abs(Vf).max() + 20.0 * noise
+    else:
+        assert np.array_equal(Vs, Vf)
+
+
 def test_ewald_alpha_choice_is_immaterial(ctx, cfg1):
     cell, Vo = cfg1
     for a in (0.4, 1.3):
