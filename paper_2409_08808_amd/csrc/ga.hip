@@ -188,7 +188,8 @@ struct WinWalk {
             const int qo = (int)__ffsll((long long)hv) - 1;
             const uint32_t vq = lane_get(bc[k], qo);
             rv[k] = lane_put(rv[k], qo, a);
-            if ((vq & 0xffu) == a) cur[k] &= ~(1ull << qo);   // q now agrees with B
+            // q now agrees with B: it leaves cur (its bit is set, so xor clears it)
+            cur[k] = (vq & 0xffu) == a ? cur[k] ^ (1ull << qo) : cur[k];
             if (take) {
                 bc[0] = lane_put(bc[0], po, b | (vq & 0xff00u));
                 bc[k] = lane_put(bc[k], qo, (vq & 0xffu) | (vp & 0xff00u));
@@ -223,7 +224,7 @@ struct WinWalk {
         for (;;) {
             while (cur[0]) {
                 const int po = (int)__ffsll((long long)cur[0]) - 1;
-                cur[0] &= cur[0] - 1;
+                cur[0] ^= 1ull << po;   // (bit po is set: it is the lowest)
                 const uint32_t a = lane_get(rv[0], po);
                 const uint32_t vp = lane_get(bc[0], po);
                 const uint32_t take = (uint32_t)(cw[0] >> po) & 1u;   // the child takes this swap of the path
