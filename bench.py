@@ -235,6 +235,22 @@ def main():
         result["mixed_vs_fp64"] = result["value"] / result["plain_fp64_trials_per_s"]
         result["mixed_vs_fp64_sweep"] = result["plain_fp64_sweep_kernel_s"] / mc_s
     run_legs(result, legs)
+    # context for the roofline: a plain 256 MiB device-to-device copy (read plus
+    # write bytes over its time, HIP events on the stream, best of five)
+    xc = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    yc = torch.empty_like(xc)
+    yc.copy_(xc)
+    best = None
+    for _ in range(5):
+        a, b = ev(torch), ev(torch)
+        a.record(stream)
+        yc.copy_(xc)
+        b.record(stream)
+        b.synchronize()
+        t = a.elapsed_time(b) * 1e-3
+        best = t if best is None else min(best, t)
+    result["device_copy_GBs"] = 2 * xc.numel() / best / 1e9
+    del xc, yc
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
